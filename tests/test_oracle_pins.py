@@ -1,0 +1,398 @@
+"""Pins of the oracle to facts the paper and the mathematics fix.
+
+Each test checks the oracle against something other than its own code: values
+printed in the paper (tests/golden/*, with citations), hand-expanded special
+cases of eq. (1.1), algebraic identities of Q_pq, brute force on tiny inputs,
+closed-form counts, and an independent cross-check.
+"""
+import json
+import random
+from math import gcd
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import poly, roots
+from tests.conftest import golden_path
+
+SMALL_PRIMES = [r for r in range(2, 100) if all(r % d for d in range(2, int(r**0.5) + 1))]
+
+
+def _read_table(name):
+    rows = []
+    with open(golden_path(name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append([int(x) for x in line.split()])
+    return np.array(rows, dtype=np.uint8)
+
+
+# ---------------------------------------------------------------- Q_pq(t) mod r
+
+def _q12_literal(t):
+    # Q_{1,2}(t) expanded by hand from eq. (1.1) with p = 1, q = 2
+    return t**10 + 90 * t**8 + 905 * t**6 + 2140 * t**4 + 1920 * t**2 - 1024
+
+
+def test_q12_closed_form():
+    rng = random.Random(1)
+    for _ in range(300):
+        t = rng.randrange(0, 10**6)
+        r = rng.choice(SMALL_PRIMES + [65521, 65519, 1000003])
+        assert oracle.q_mod_r(1, 2, t, r) == _q12_literal(t) % r
+        assert poly.q_value(1, 2, t) == _q12_literal(t)
+
+
+def test_q_pp_factorization():
+    # p = q: Q_pp(t) = -(p^2 - t)(p^2 + t)(p^4 + t^2)^4
+    rng = random.Random(2)
+    for _ in range(300):
+        p, t = rng.randrange(0, 5000), rng.randrange(0, 10**6)
+        r = rng.choice(SMALL_PRIMES + [65521, 40009])
+        ref = -(p * p - t) * (p * p + t) * (p**4 + t * t) ** 4
+        assert oracle.q_mod_r(p, p, t, r) == ref % r
+        assert poly.q_value(p, p, t) == ref
+
+
+def test_q_axes():
+    # q = 0: Q = t^6 (t^2 - p^4)^2 ;  p = 0: Q = t^6 (t^4 + 6 q^4 t^2 + q^8)
+    rng = random.Random(3)
+    for _ in range(200):
+        a, t = rng.randrange(0, 3000), rng.randrange(0, 10**5)
+        r = rng.choice(SMALL_PRIMES + [65521])
+        assert oracle.q_mod_r(a, 0, t, r) == (t**6 * (t * t - a**4) ** 2) % r
+        assert oracle.q_mod_r(0, a, t, r) == (t**6 * (t**4 + 6 * a**4 * t * t + a**8)) % r
+
+
+def test_weighted_homogeneity():
+    # Q_{lp, lq}(l^2 t) = l^20 Q_pq(t): p, q of weight 1, t of weight 2
+    rng = random.Random(4)
+    for _ in range(200):
+        p, q, t, lam = (rng.randrange(0, 300) for _ in range(4))
+        assert poly.q_value(lam * p, lam * q, lam * lam * t) == lam**20 * poly.q_value(p, q, t)
+        r = rng.choice(SMALL_PRIMES)
+        assert oracle.q_mod_r(lam * p, lam * q, lam * lam * t, r) == \
+            (pow(lam, 20, r) * oracle.q_mod_r(p, q, t, r)) % r
+
+
+def test_inversion_symmetry():
+    # t^10 Q_pq((pq)^2 / t) = -(pq)^10 Q_qp(t), checked on coefficients:
+    # sum_k c_k(p,q) (pq)^(4k) t^(10-2k) = -(pq)^10 sum_k c_k(q,p) t^(2k)
+    rng = random.Random(5)
+    for _ in range(100):
+        p, q = rng.randrange(1, 500), rng.randrange(1, 500)
+        a = poly.q_coeffs(p, q)
+        b = poly.q_coeffs(q, p)
+        m = p * q
+        for k in range(6):
+            # coefficient of t^(10-2k) on the left vs on the right
+            assert a[k] * m ** (4 * k) == -(m**10) * b[5 - k]
+    # and modulo r through the C oracle, t invertible
+    for _ in range(300):
+        p, q = rng.randrange(1, 10**4), rng.randrange(1, 10**4)
+        r = rng.choice([x for x in SMALL_PRIMES if x > 2])
+        t = rng.randrange(1, r)
+        if (p * q) % r == 0:
+            continue
+        x = (pow(p * q, 2, r) * pow(t, -1, r)) % r
+        lhs = (pow(t, 10, r) * oracle.q_mod_r(p, q, x, r)) % r
+        rhs = (-pow(p * q, 10, r) * oracle.q_mod_r(q, p, t, r)) % r
+        assert lhs == rhs
+
+
+def test_even_in_t_and_reduction():
+    rng = random.Random(6)
+    for _ in range(300):
+        p, q = rng.randrange(0, 10**9), rng.randrange(0, 10**9)
+        r = rng.choice(SMALL_PRIMES + [65521])
+        t = rng.randrange(0, r)
+        v = oracle.q_mod_r(p, q, t, r)
+        assert v == oracle.q_mod_r(p, q, (r - t) % r, r)
+        assert v == oracle.q_mod_r(p % r, q % r, t, r)   # eq. (2.1)-(2.2)
+        assert v == poly.q_value(p % r, q % r, t) % r
+
+
+# ---------------------------------------------------------------- tables
+
+def test_u11_matches_paper():
+    assert np.array_equal(oracle.table(11), _read_table("u11_table.txt"))
+
+
+def test_u2_matches_paper_and_trivial_primes():
+    assert np.array_equal(oracle.table(2), _read_table("u2_table.txt"))
+    with open(golden_path("paper_constants.json")) as f:
+        trivial = json.load(f)["trivial_primes"]["primes"]
+    for r in trivial:
+        assert oracle.table(r).sum() == 0, r
+    # and 11 is the first prime that rejects anything
+    assert oracle.table(11).sum() > 0
+
+
+def test_u11_packing_matches_paper():
+    with open(golden_path("u11_packed.json")) as f:
+        g = json.load(f)
+    b = oracle.pack(11)
+    assert len(b) == g["n_bytes"]
+    for idx, bits in g["shown_msb_first"].items():
+        assert format(b[int(idx)], "08b") == bits, idx
+
+
+def test_pack_layout_round_trip():
+    for r in (13, 17, 31, 97):
+        u = oracle.table(r)
+        b = np.frombuffer(oracle.pack(r), dtype=np.uint8)
+        assert len(b) == (r * r + 7) // 8
+        bits = np.unpackbits(b, bitorder="little")[: r * r].reshape(r, r)
+        assert np.array_equal(bits, u)
+        assert np.unpackbits(b, bitorder="little")[r * r:].sum() == 0
+
+
+@pytest.mark.parametrize("r", [x for x in SMALL_PRIMES if x >= 3])
+def test_table_invariants(r):
+    u = oracle.table(r).astype(np.int64)
+    a = np.arange(r)
+    assert np.array_equal(u, u.T)                        # u(a,b) = u(b,a)
+    assert np.array_equal(u, u[(-a) % r, :])             # u(a,b) = u(-a,b)
+    assert u[0, :].sum() == 0 and u[:, 0].sum() == 0     # Q(0) = -(pq)^10, t=0 root
+    assert u[a, a].sum() == 0                            # Q_pp has the root t = p^2
+    assert u[a, (-a) % r].sum() == 0
+    for lam in range(2, min(r, 6)):                      # weight-20 homogeneity
+        assert np.array_equal(u, u[(lam * a) % r][:, (lam * a) % r])
+
+
+def test_table_density_by_ratio_classes(golden):
+    # For a, b != 0, u_r(a, b) depends only on a/b (homogeneity), so
+    # popcount(u_r) = (r - 1) * #{x != 0 : Q_{x,1}(t) has no root mod r}.
+    # The right side is counted here with exact Python integers.
+    cross = golden("survey_crosscheck.json")["densities"]
+    for r in [x for x in SMALL_PRIMES if 11 <= x < 60]:
+        n_unsolv = 0
+        for x in range(1, r):
+            if all(poly.q_value(x, 1, t) % r for t in range(r)):
+                n_unsolv += 1
+        assert int(oracle.table(r).sum()) == (r - 1) * n_unsolv, r
+        assert int(oracle.table(r).sum()) == cross[str(r)], r
+    for r in (61, 67, 97):
+        assert int(oracle.table(r).sum()) == cross[str(r)]
+
+
+# ---------------------------------------------------------------- sieve
+
+def _mobius_upto(n):
+    mu = [1] * (n + 1)
+    is_comp = [False] * (n + 1)
+    primes = []
+    mu[0] = 0
+    for i in range(2, n + 1):
+        if not is_comp[i]:
+            primes.append(i)
+            mu[i] = -1
+        for pr in primes:
+            if i * pr > n:
+                break
+            is_comp[i * pr] = True
+            if i % pr == 0:
+                mu[i * pr] = 0
+                break
+            mu[i * pr] = -mu[i]
+    return mu
+
+
+def coprime_pairs(p0, p1, q0, q1):
+    """#{p0<=p<=p1, q0<=q<=q1 : gcd(p,q) = 1, p != q}, by Moebius inversion."""
+    n = max(p1, q1)
+    mu = _mobius_upto(n)
+    tot = 0
+    for d in range(1, n + 1):
+        if mu[d]:
+            tot += mu[d] * (p1 // d - (p0 - 1) // d) * (q1 // d - (q0 - 1) // d)
+    if p0 <= 1 <= p1 and q0 <= 1 <= q1:
+        tot -= 1   # (1, 1) is coprime but p = q
+    return tot
+
+
+def _brute(p0, p1, q0, q1, primes):
+    """Sieve by direct evaluation of Q_pq(t) mod r for every t: no tables."""
+    asc = sorted(primes)
+    counts = {r: 0 for r in asc}
+    surv, n = [], 0
+    width = q1 - q0 + 1
+    for p in range(p0, p1 + 1):
+        for q in range(q0, q1 + 1):
+            if p == q or gcd(p, q) != 1:
+                continue
+            n += 1
+            for r in asc:
+                if all(poly.q_value(p % r, q % r, t) % r for t in range(r)):
+                    counts[r] += 1
+                    break
+            else:
+                surv.append((p - p0) * width + (q - q0))
+    return n, [counts[r] for r in primes], surv
+
+
+def test_sieve_brute_force_tiny():
+    primes = [3, 5, 7, 11, 13, 17, 19, 23, 29, 31]
+    for rect in [(1, 30, 1, 30), (5, 17, 2, 29), (1, 1, 1, 30), (7, 7, 7, 7), (12, 30, 1, 3)]:
+        n, counts, surv = _brute(*rect, primes)
+        res = oracle.sieve(*rect, primes)
+        assert res["n_pairs"] == n
+        assert res["counts"].tolist() == counts
+        assert res["survivors"].tolist() == surv
+
+
+def test_sieve_brute_force_unsorted_primes():
+    primes = [13, 2, 11, 29, 5, 17]
+    n, counts, surv = _brute(1, 24, 1, 24, primes)
+    res = oracle.sieve(1, 24, 1, 24, primes)
+    assert (res["n_pairs"], res["counts"].tolist(), res["survivors"].tolist()) == (n, counts, surv)
+
+
+@pytest.mark.parametrize("rect", [(1, 200, 1, 200), (1, 10**4, 1, 10**4), (37, 911, 5, 1200),
+                                  (1, 1, 1, 1), (2, 2, 1, 5), (999, 1500, 998, 1003)])
+def test_n_pairs_moebius(rect):
+    res = oracle.sieve(*rect, [3, 5, 7, 11, 13])
+    assert res["n_pairs"] == coprime_pairs(*rect)
+    assert int(res["counts"].sum()) + res["n_survivors"] == res["n_pairs"]
+
+
+def test_sieve_square_symmetry():
+    primes = [11, 13, 17, 19, 23]
+    res = oracle.sieve(1, 300, 1, 300, primes)
+    pairs = {(1 + i // 300, 1 + i % 300) for i in res["survivors"].tolist()}
+    assert pairs == {(q, p) for p, q in pairs}
+
+
+def test_sieve_matches_crosscheck(golden):
+    cross = golden("survey_crosscheck.json")
+    c1 = cross["c1"]
+    res = oracle.sieve(*c1["rect"], c1["primes"])
+    assert res["n_pairs"] == c1["n_pairs"] and res["counts"].tolist() == c1["counts"]
+    got = [(1 + i // 200, 1 + i % 200) for i in res["survivors"].tolist()]
+    assert got == [tuple(x) for x in c1["survivors_pq"]]
+    c2 = cross["c2"]
+    g2 = golden("oracle_c2.json")
+    assert g2["n_pairs"] == c2["n_pairs"] and g2["counts"] == c2["counts"]
+    assert [(1 + i // 10**4, 1 + i % 10**4) for i in g2["survivors"]] == \
+        [tuple(x) for x in c2["survivors_pq"]]
+
+
+def test_golden_c3_conservation(golden):
+    try:
+        g = golden("oracle_c3.json")
+    except FileNotFoundError:
+        pytest.skip("c3 golden not generated")
+    assert g["n_pairs"] == golden("survey_crosscheck.json")["c3"]["n_pairs"]
+    assert sum(g["counts"]) + g["n_survivors"] == g["n_pairs"]
+    assert g["counts"][:3] == [0, 0, 0]
+
+
+# ---------------------------------------------------------------- region (1.2)
+
+def test_region_lower_bound():
+    with open(golden_path("paper_constants.json")) as f:
+        c = json.load(f)
+    # Start_searching(152, 3): the least q of (5.2) at p = 152 is 3
+    assert oracle.region_qmin(c["start_searching"]["p"]) == c["start_searching"]["q"]
+    for p in range(1, 3000):
+        # (5.1) for p <= 151: q >= p/59 ; (5.2) for p >= 152: q >= cbrt(p/9)
+        lo = -(-p // 59) if p <= 151 else next(q for q in range(1, p) if 9 * q**3 >= p)
+        assert oracle.region_qmin(p) == lo, p
+
+
+def test_paper_section6_arithmetic():
+    with open(golden_path("paper_constants.json")) as f:
+        c = json.load(f)
+    assert sum(59 * p for p in range(1, 154001)) == c["pairs_tested"]["value"]
+    dt = c["time_per_pair_s"]["minutes"] * 60 / c["pairs_tested"]["value"]
+    assert abs(dt - c["time_per_pair_s"]["value"]) < 0.005e-7
+    assert 2**32 // 59 == c["p_max_32bit"]["value"]
+    primes = [r for r in range(11, 542) if all(r % d for d in range(2, int(r**0.5) + 1))]
+    assert len(primes) == c["sieve_primes"]["count"] and primes[-1] == 541
+    assert primes[c["max_depth"]["index"] - 1] == c["max_depth"]["prime"]
+
+
+def test_region_small_slices(golden):
+    cross = golden("survey_crosscheck.json")["region"]
+    primes = [r for r in range(11, 542) if all(r % d for d in range(2, int(r**0.5) + 1))]
+    lo = oracle.sieve_region(1, 151, primes)
+    assert primes[lo["max_depth"] - 1] == cross["p_le_151"]["max_prime"]
+    hi = oracle.sieve_region(152, 1151, primes)
+    assert hi["n_survivors"] == cross["p_152_1151"]["survivors"]
+    assert primes[hi["max_depth"] - 1] == cross["p_152_1151"]["max_prime"]
+    assert int(hi["counts"].sum()) + hi["n_survivors"] == hi["n_pairs"]
+
+
+# ---------------------------------------------------------------- roots
+
+def _expand(roots_, extra=()):
+    a = [1]
+    for x in roots_:
+        a = [(a[i - 1] if i else 0) - x * (a[i] if i < len(a) else 0) for i in range(len(a) + 1)]
+    for f in extra:   # multiply by an integer polynomial with no integer roots
+        b = [0] * (len(a) + len(f) - 1)
+        for i, u in enumerate(a):
+            for j, v in enumerate(f):
+                b[i + j] += u * v
+        a = b
+    return a
+
+
+def test_integer_roots_planted():
+    rng = random.Random(7)
+    for _ in range(200):
+        k = rng.randrange(1, 5)
+        planted = [rng.randrange(-10**12, 10**12) for _ in range(k)]
+        if rng.random() < 0.3:
+            planted.append(planted[0])          # a double root: no sign change
+        extra = rng.choice([(), ([1, 0, 1],), ([3, 0, 1],), ([2, -2, 1],)])
+        a = _expand(planted, extra)
+        scale = rng.choice([1, -1, 7])
+        a = [c * scale for c in a]
+        assert roots.integer_roots(a) == sorted(set(planted))
+
+
+def test_integer_roots_close_irrationals():
+    # x^2 - 2 y^2 near-misses: no integer roots, two close real roots
+    for m in (10**6, 10**9 + 7, 2**40):
+        a = [-(2 * m * m + 1), 0, 1]      # roots +-sqrt(2 m^2 + 1), irrational
+        assert roots.integer_roots(a) == []
+        b = _expand([m, m + 1])
+        assert roots.integer_roots(b) == [m, m + 1]
+
+
+def test_positive_roots_degenerate_pairs():
+    for p in (1, 2, 3, 10, 97, 1000, 65537, 2**30 - 1):
+        assert roots.positive_t_roots(p, p) == [p * p]      # Q_pp: root t = p^2
+        assert roots.positive_t_roots(p, 0) == [p * p]      # Q_p0: root t = p^2
+        assert roots.positive_t_roots(0, p) == []
+
+
+def test_no_roots_small_coprime_pairs_sympy():
+    sympy = pytest.importorskip("sympy")
+    t = sympy.Symbol("t")
+    for p in range(1, 13):
+        for q in range(1, 13):
+            if p == q or gcd(p, q) != 1:
+                continue
+            expr = sum(c * t ** (2 * k) for k, c in enumerate(poly.q_coeffs(p, q)))
+            _, factors = sympy.factor_list(expr)
+            assert len(factors) == 1 and factors[0][1] == 1, (p, q)   # irreducible
+            assert roots.positive_t_roots(p, q) == []
+
+
+def test_no_roots_coprime_upto_30():
+    for p in range(1, 31):
+        for q in range(1, 31):
+            if p != q and gcd(p, q) == 1:
+                assert roots.positive_t_roots(p, q) == []
+
+
+def test_theorem_1_1_flags():
+    assert poly.theorem_1_1_flags(12, 12, 144) == 8
+    assert poly.theorem_1_1_flags(1, 2, 5) == 1 | 2 | 4
+    # (1 + 5)(2 + 5) = 42 > 50 is false
+    assert poly.theorem_1_1_flags(1, 2, 5) & 8 == 0
+    assert poly.theorem_1_1_flags(2, 1, 3) == 2 | 4 | 8
