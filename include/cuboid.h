@@ -1,0 +1,254 @@
+/*
+ * cuboid.h — C interface of the MI355X (gfx950) modulo-primes sieve for
+ * perfect cuboids (second cuboid conjecture).
+ *
+ * The method is that of R.R. Gallyamov, I.R. Kadyrov, D.D. Kashelevskiy,
+ * N.G. Kutlugallyamov, R.A. Sharipov, "A fast modulo primes algorithm for
+ * searching perfect cuboids and its implementation", arXiv:1601.00636:
+ *
+ *   - Q_pq(t) is the even tenth-degree polynomial of eq. (1.1);
+ *   - a pair (p~, q~) of residues modulo a prime r is "unsolvable" when no
+ *     t~ in [0, r) makes Q_{p~q~}(t~) vanish modulo r (Definition 1.1); the
+ *     unsolvability bit u_r(p~, q~) of eq. (2.3) is 1 for such pairs;
+ *   - a pair (p, q) for which some sieve prime r has u_r(p mod r, q mod r) = 1
+ *     has no integer root t (section 2) and is rejected; the rest survive;
+ *   - by Theorem 1.1 a perfect cuboid of this family needs a positive integer
+ *     root t of Q_pq with t > p^2, t > pq, t > q^2, (p^2 + t)(pq + t) > 2t^2.
+ *
+ * Conventions for every function below:
+ *   - Return value: a cuboid_status code (0 = CUBOID_OK) unless stated.  The
+ *     numbering reuses the paper's return codes where the meaning matches
+ *     (section 5: 1 = already running / busy, 6 = tables not loaded).
+ *   - Buffers: all pointers are HOST memory owned by the caller, unless a
+ *     parameter says "device".  The library never keeps a caller pointer after
+ *     the call returns (except the server, see cuboid_server_submit).
+ *   - The library owns the context, its device tables and device scratch.
+ *   - `hip_stream` is a hipStream_t (as void*); NULL means the context's own
+ *     stream.  Calls that return host results synchronise that stream before
+ *     returning.
+ *   - Misuse (null pointers, destroyed context, bad ranges) is reported by a
+ *     status code and never crashes, as the paper's DLL promises (section 5).
+ *   - One context may be used from several host threads; calls on one context
+ *     are serialised internally.
+ */
+#ifndef CUBOID_H
+#define CUBOID_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum cuboid_status {
+    CUBOID_OK = 0,
+    CUBOID_E_BUSY = 1,        /* work in flight, or a server still running       */
+    CUBOID_E_RANGE = 2,       /* empty/inverted bounds or a bound equal to 0      */
+    CUBOID_E_LIMIT = 3,       /* a size limit exceeded (see each function)        */
+    CUBOID_E_PRIMES = 4,      /* prime list: empty, non-prime, duplicate, >= 2^16 */
+    CUBOID_E_CAPACITY = 5,    /* output buffer too small; required size returned  */
+    CUBOID_E_NOT_LOADED = 6,  /* null or destroyed context                        */
+    CUBOID_E_DEVICE = 7,      /* no usable gfx950 device, or a HIP runtime error  */
+    CUBOID_E_ARG = 8          /* null pointer or invalid argument                 */
+} cuboid_status;
+
+typedef struct cuboid_ctx cuboid_ctx;
+
+/* Short English text for a status code (static storage). */
+const char *cuboid_status_string(int status);
+
+/* Library version string, e.g. "0.1.0 gfx950" (static storage). */
+const char *cuboid_version(void);
+
+/*
+ * Create a context on HIP device `hip_device`: allocates the constant device
+ * tables (small-prime list, coprimality wheel).  Unsolvability tables are
+ * built on the GPU the first time a prime set is used and then stay resident
+ * (the analogue of the paper's Load_Cuboid_Binaries, section 4).
+ * Errors: E_ARG (out == NULL), E_DEVICE (no device / not gfx950 / HIP error).
+ */
+int cuboid_create(cuboid_ctx **out, int hip_device);
+
+/*
+ * Destroy a context and free its device memory (cf. Release_Cuboid_Binaries,
+ * section 5).  Returns E_BUSY, destroying nothing, while a call or a server
+ * is still using it; E_NOT_LOADED for NULL.
+ */
+int cuboid_destroy(cuboid_ctx *ctx);
+
+/*
+ * Evaluate Q_pq(t) mod r (eq. 1.1 reduced as in eq. 2.2) on the GPU for n
+ * quadruples: out[i] = Q_{p[i] q[i]}(t[i]) mod r[i].  The analogue of the
+ * paper's Calculate_Q_pq_mod_prime (section 3), which handles 16-bit moduli.
+ * p, q, t: any uint32; r: 2 <= r < 65536 (any integer, prime or not).
+ * Errors: E_ARG (null pointer with n > 0, an r out of range), E_DEVICE.
+ */
+int cuboid_q_mod_prime(cuboid_ctx *ctx, const uint32_t *p, const uint32_t *q,
+                       const uint32_t *t, const uint32_t *r, uint64_t n, uint32_t *out);
+
+/*
+ * The unsolvability table u_r of eq. (2.3) for one prime r, built on the GPU,
+ * in the byte packing of eq. (2.6): bit a*r + b holds u_r(a, b) (a = p~ row,
+ * b = q~ column), eight bits per byte least-significant first, the last byte
+ * zero-padded; ceil(r*r/8) bytes.
+ * *written receives the byte count (also when cap is too small).
+ * Errors: E_PRIMES (r not a prime below 65536), E_CAPACITY (cap too small),
+ * E_ARG, E_DEVICE.
+ */
+int cuboid_table_bytes(cuboid_ctx *ctx, uint32_t r, uint8_t *out, size_t cap, size_t *written);
+
+/*
+ * The sieve over the rectangle p0 <= p <= p1, q0 <= q <= q1 (inclusive,
+ * uint32 coordinates >= 1).
+ *
+ * Domain: pairs with p != q and gcd(p, q) = 1 (Conjecture 1.1); their number is
+ * written to *n_pairs.  A pair is rejected by the FIRST prime r, in ascending
+ * order of the prime list, with u_r(p mod r, q mod r) = 1, and counts[i] (for
+ * primes[i]) counts the pairs so rejected; primes whose table is all zero
+ * (2, 3, 5, 7: section 2) always count 0.  The primes may be given in any
+ * order; counts[] follows the order given.
+ * Survivors (pairs no prime rejects) are written to survivors[] as ascending
+ * uint64 indices (p - p0) * (q1 - q0 + 1) + (q - q0); *n_survivors receives
+ * their number.  sum(counts) + *n_survivors == *n_pairs always.
+ *
+ * primes: 1 <= n_primes <= 6542 distinct primes, each < 65536.
+ * survivors may be NULL when cap == 0.
+ * Errors: E_RANGE (p0 > p1, q0 > q1, or p0 == 0 or q0 == 0), E_PRIMES,
+ * E_CAPACITY (more than cap survivors: *n_survivors is set to the number
+ * needed, counts/n_pairs are valid, survivors[] contents are unspecified),
+ * E_LIMIT (unsolvability tables for the prime set exceed the device budget),
+ * E_ARG, E_DEVICE, E_NOT_LOADED.
+ */
+int cuboid_sieve_range(cuboid_ctx *ctx, uint32_t p0, uint32_t p1, uint32_t q0, uint32_t q1,
+                       const uint32_t *primes, uint32_t n_primes,
+                       uint64_t *survivors, uint64_t cap, uint64_t *n_survivors,
+                       uint64_t *counts, uint64_t *n_pairs, void *hip_stream);
+
+/*
+ * One positive integer root of Q_pq (eq. 1.1) confirmed in exact arithmetic.
+ * flags: bit 0 t > p^2, bit 1 t > pq, bit 2 t > q^2,
+ *        bit 3 (p^2 + t)(pq + t) > 2 t^2  (the inequalities of Theorem 1.1);
+ * all four set means (p, q, t) yields a perfect cuboid.
+ */
+typedef struct cuboid_root {
+    uint32_t p, q;
+    uint64_t t;
+    uint32_t flags;
+    uint32_t input_index;   /* position of (p, q) in the input arrays */
+} cuboid_root;
+
+/*
+ * Exact integer-root check for n pairs (typically sieve survivors).
+ * For every i, all integers t > 0 with Q_{p[i] q[i]}(t) = 0 are reported.
+ * GPU part: t^2 divides the constant term p^10 q^10 of Q as a polynomial in
+ * t^2 (p^8 or q^8 when the other is 0), so t runs over the divisors of
+ * p^5 q^5 up to a root bound; each candidate is evaluated modulo three 62-bit
+ * primes.  CPU part: candidates that vanish modulo all three are confirmed in
+ * exact multiprecision arithmetic.  Roots are listed by input index, then by t.
+ * p[i], q[i] < 2^31 (so every root is below 2^64).  p[i] = q[i] = 0 has no
+ * positive roots.
+ * Errors: E_LIMIT (a coordinate >= 2^31, or more than 2^40 candidates for one
+ * pair), E_CAPACITY (*n_roots set to the number needed), E_ARG, E_DEVICE.
+ */
+int cuboid_root_check(cuboid_ctx *ctx, const uint32_t *p, const uint32_t *q, uint64_t n,
+                      cuboid_root *roots, uint64_t cap, uint64_t *n_roots);
+
+/*
+ * Exact CPU confirmation alone (no GPU): *is_root = 1 iff Q_pq(t) == 0 in
+ * exact integer arithmetic; *flags as in cuboid_root.  p, q < 2^31.
+ * Errors: E_ARG, E_LIMIT.
+ */
+int cuboid_exact_check(uint32_t p, uint32_t q, uint64_t t, int *is_root, uint32_t *flags);
+
+/*
+ * Q_pq(t) in exact integer arithmetic on the CPU, as a signed decimal string
+ * with its terminating NUL (for checking the exact arithmetic).  p, q < 2^31.
+ * Errors: E_ARG, E_LIMIT, E_CAPACITY (cap too small for the string).
+ */
+int cuboid_exact_value(uint32_t p, uint32_t q, uint64_t t, char *out, size_t cap);
+
+/*
+ * Prime-list canonicalisation alone (no GPU): validates `primes` and writes
+ * them in ascending order to sorted_out[n] and, for each, whether its table is
+ * known to be all zero by the paper's statement (2, 3, 5, 7: section 2) to
+ * trivial_out[n] (may be NULL).  Errors: E_PRIMES, E_ARG.
+ */
+int cuboid_canonical_primes(const uint32_t *primes, uint32_t n, uint32_t *sorted_out,
+                            uint8_t *trivial_out);
+
+/* ------------------------------------------------------------------ batched */
+
+typedef struct cuboid_request {
+    uint32_t p0, p1, q0, q1;      /* inclusive rectangle, coordinates >= 1 */
+} cuboid_request;
+
+typedef struct cuboid_result {
+    uint64_t *survivors;          /* caller buffer, ascending indices as in cuboid_sieve_range */
+    uint64_t cap;                 /* its capacity                                  */
+    uint64_t n_survivors;         /* out: number of survivors (may exceed cap)      */
+    uint64_t *counts;             /* caller buffer [n_primes], order of the prime list */
+    uint64_t n_pairs;             /* out                                            */
+    int32_t status;               /* out: CUBOID_OK, CUBOID_E_CAPACITY or CUBOID_E_RANGE */
+    uint32_t reserved;
+} cuboid_result;
+
+/*
+ * Many rectangles in one persistent launch: every request's outputs are those
+ * cuboid_sieve_range would give for it alone (bit-exact).  Work is split into
+ * 64-row x 64-column units and spread evenly over the whole GPU regardless of
+ * request sizes.  Returns E_CAPACITY if any request's status is E_CAPACITY
+ * (the others are complete); an invalid rectangle sets that request's status
+ * to E_RANGE and fails the call with E_RANGE before any work.  Returns E_LIMIT
+ * (with every n_survivors still exact) if the survivors of the whole batch
+ * exceed 2^26.
+ * Errors: as cuboid_sieve_range, plus E_ARG for n_req == 0 or NULL arrays.
+ */
+int cuboid_sieve_batch(cuboid_ctx *ctx, const cuboid_request *req, uint32_t n_req,
+                       const uint32_t *primes, uint32_t n_primes,
+                       cuboid_result *res, void *hip_stream);
+
+/* ------------------------------------------------------------------ tuning */
+
+typedef struct cuboid_tuning {
+    uint32_t dense_primes;   /* K: leading non-trivial primes tested as 64-wide bit windows */
+    uint32_t workgroups;     /* persistent grid size (0 = two per compute unit) */
+    uint32_t lds_budget;     /* bytes of LDS allowed for the dense windows      */
+    uint32_t reserved;
+} cuboid_tuning;
+
+/*
+ * Time candidate tunings for `primes` on a sample rectangle and keep the
+ * fastest for this context; if cache_path is non-NULL the choice is read from
+ * / appended to that JSON-lines file, keyed by device architecture and prime
+ * set.  Results never depend on the tuning.  out may be NULL.
+ */
+int cuboid_autotune(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes,
+                    const char *cache_path, cuboid_tuning *out);
+
+/* Set (NULL = restore defaults) or read the tuning used for `primes`. */
+int cuboid_set_tuning(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes,
+                      const cuboid_tuning *tuning);
+int cuboid_get_tuning(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes,
+                      cuboid_tuning *out);
+
+/* ------------------------------------------------------------------ timing */
+
+typedef struct cuboid_timing {
+    double sweep_ms;         /* sieve sweep kernel, HIP events on the call's stream */
+    double total_gpu_ms;     /* first to last kernel of the call                */
+    uint64_t units;          /* 64 x 64 work units the sweep processed          */
+    uint32_t dense_primes;   /* K used                                          */
+    uint32_t workgroups;     /* grid used                                       */
+} cuboid_timing;
+
+/* Turn per-call HIP-event timing on (1) or off (0). */
+int cuboid_enable_timing(cuboid_ctx *ctx, int on);
+/* Timing of the last sieve call on this context. */
+int cuboid_last_timing(cuboid_ctx *ctx, cuboid_timing *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CUBOID_H */

@@ -1,0 +1,318 @@
+"""Thin ctypes binding over libcuboid.so with the C interface's names
+(include/cuboid.h).  Argument marshalling only: every step of the sieve runs in
+the library's HIP kernels.  Raises CuboidError for non-zero status codes.
+
+Streams: pass a torch.cuda.Stream, a raw hipStream_t integer, or None (the
+context's own stream).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcuboid.so")
+
+OK, E_BUSY, E_RANGE, E_LIMIT, E_PRIMES, E_CAPACITY, E_NOT_LOADED, E_DEVICE, E_ARG = range(9)
+
+u8, u32, u64, i32 = ctypes.c_uint8, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+P = ctypes.POINTER
+
+
+class cuboid_root(ctypes.Structure):
+    _fields_ = [("p", u32), ("q", u32), ("t", u64), ("flags", u32), ("input_index", u32)]
+
+
+class cuboid_request(ctypes.Structure):
+    _fields_ = [("p0", u32), ("p1", u32), ("q0", u32), ("q1", u32)]
+
+
+class cuboid_result(ctypes.Structure):
+    _fields_ = [("survivors", P(u64)), ("cap", u64), ("n_survivors", u64), ("counts", P(u64)),
+                ("n_pairs", u64), ("status", ctypes.c_int32), ("reserved", u32)]
+
+
+class cuboid_tuning(ctypes.Structure):
+    _fields_ = [("dense_primes", u32), ("workgroups", u32), ("lds_budget", u32), ("reserved", u32)]
+
+
+class cuboid_timing(ctypes.Structure):
+    _fields_ = [("sweep_ms", ctypes.c_double), ("total_gpu_ms", ctypes.c_double), ("units", u64),
+                ("dense_primes", u32), ("workgroups", u32)]
+
+
+class cuboid_server_config(ctypes.Structure):
+    _fields_ = [("streams", u32), ("max_inflight_units", u64), ("hbm_budget_bytes", u64),
+                ("max_batch_requests", u32), ("reserved", u32)]
+
+
+class cuboid_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", u64), ("completed", u64), ("launches", u64), ("units", u64),
+                ("max_concurrent_requests", u32), ("reserved", u32)]
+
+
+class CuboidError(RuntimeError):
+    def __init__(self, status, what="", needed=None):
+        self.status = status
+        self.needed = needed
+        text = _lib.cuboid_status_string(status).decode() if _lib else str(status)
+        super().__init__("%s: status %d (%s)" % (what, status, text))
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libcuboid.so is not built (run paper_1601_00636_amd.build.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    sigs = {
+        "cuboid_status_string": ([i32], ctypes.c_char_p),
+        "cuboid_version": ([], ctypes.c_char_p),
+        "cuboid_create": ([P(vp), i32], i32),
+        "cuboid_destroy": ([vp], i32),
+        "cuboid_q_mod_prime": ([vp, P(u32), P(u32), P(u32), P(u32), u64, P(u32)], i32),
+        "cuboid_table_bytes": ([vp, u32, P(u8), ctypes.c_size_t, P(ctypes.c_size_t)], i32),
+        "cuboid_sieve_range": ([vp, u32, u32, u32, u32, P(u32), u32, P(u64), u64, P(u64), P(u64),
+                                P(u64), vp], i32),
+        "cuboid_root_check": ([vp, P(u32), P(u32), u64, P(cuboid_root), u64, P(u64)], i32),
+        "cuboid_exact_check": ([u32, u32, u64, P(i32), P(u32)], i32),
+        "cuboid_exact_value": ([u32, u32, u64, ctypes.c_char_p, ctypes.c_size_t], i32),
+        "cuboid_canonical_primes": ([P(u32), u32, P(u32), P(u8)], i32),
+        "cuboid_sieve_batch": ([vp, P(cuboid_request), u32, P(u32), u32, P(cuboid_result), vp], i32),
+        "cuboid_autotune": ([vp, P(u32), u32, ctypes.c_char_p, P(cuboid_tuning)], i32),
+        "cuboid_set_tuning": ([vp, P(u32), u32, P(cuboid_tuning)], i32),
+        "cuboid_get_tuning": ([vp, P(u32), u32, P(cuboid_tuning)], i32),
+        "cuboid_enable_timing": ([vp, i32], i32),
+        "cuboid_last_timing": ([vp, P(cuboid_timing)], i32),
+        "cuboid_server_start": ([vp, P(u32), u32, P(cuboid_server_config), P(vp)], i32),
+        "cuboid_server_submit": ([vp, P(cuboid_request), P(u64)], i32),
+        "cuboid_server_poll": ([vp, u64, P(cuboid_result), i32], i32),
+        "cuboid_server_stats": ([vp, P(cuboid_server_stats)], i32),
+        "cuboid_server_stop": ([vp], i32),
+    }
+    for name, (args, res) in sigs.items():
+        fn = getattr(lib, name, None)
+        if fn is None:
+            continue
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def lib():
+    return _load()
+
+
+def exported_symbols():
+    """Names of the C entry points this binding knows."""
+    _load()
+    return [n for n in dir(_lib) if n.startswith("cuboid_")]
+
+
+def _arr(a, dtype):
+    a = np.ascontiguousarray(np.asarray(a, dtype=dtype))
+    return a
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(P(ct))
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _check(st, what, needed=None):
+    if st != OK:
+        raise CuboidError(st, what, needed)
+
+
+# ---------------------------------------------------------------- functions
+
+def cuboid_status_string(status):
+    return _load().cuboid_status_string(int(status)).decode()
+
+
+def cuboid_version():
+    return _load().cuboid_version().decode()
+
+
+def cuboid_create(device=0):
+    h = ctypes.c_void_p()
+    _check(_load().cuboid_create(ctypes.byref(h), int(device)), "cuboid_create")
+    return h
+
+
+def cuboid_destroy(ctx):
+    return _load().cuboid_destroy(ctx)
+
+
+def cuboid_q_mod_prime(ctx, p, q, t, r):
+    p, q, t, r = (_arr(x, np.uint32) for x in (p, q, t, r))
+    n = len(p)
+    out = np.zeros(n, dtype=np.uint32)
+    _check(_load().cuboid_q_mod_prime(ctx, _p(p, u32), _p(q, u32), _p(t, u32), _p(r, u32), n,
+                                      _p(out, u32)), "cuboid_q_mod_prime")
+    return out
+
+
+def cuboid_table_bytes(ctx, r):
+    written = ctypes.c_size_t(0)
+    st = _load().cuboid_table_bytes(ctx, int(r), None, 0, ctypes.byref(written))
+    if st not in (OK, E_CAPACITY):
+        _check(st, "cuboid_table_bytes")
+    buf = np.zeros(max(1, written.value), dtype=np.uint8)
+    _check(_load().cuboid_table_bytes(ctx, int(r), _p(buf, u8), buf.size, ctypes.byref(written)),
+           "cuboid_table_bytes")
+    return bytes(buf[:written.value])
+
+
+def cuboid_sieve_range(ctx, p0, p1, q0, q1, primes, cap=1 << 20, stream=None):
+    """dict(counts, n_pairs, survivors, n_survivors); raises CuboidError."""
+    pr = _arr(primes, np.uint32)
+    counts = np.zeros(max(1, len(pr)), dtype=np.uint64)
+    surv = np.zeros(max(1, cap), dtype=np.uint64)
+    ns, npairs = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    st = _load().cuboid_sieve_range(ctx, int(p0), int(p1), int(q0), int(q1), _p(pr, u32), len(pr),
+                                    _p(surv, u64), int(cap), ctypes.byref(ns), _p(counts, u64),
+                                    ctypes.byref(npairs), _stream(stream))
+    _check(st, "cuboid_sieve_range", needed=ns.value if st == E_CAPACITY else None)
+    return dict(counts=counts[:len(pr)], n_pairs=npairs.value, n_survivors=ns.value,
+                survivors=surv[:ns.value].copy())
+
+
+def cuboid_root_check(ctx, p, q, cap=1 << 16):
+    """List of (p, q, t, flags, input_index) for every positive integer root."""
+    p, q = _arr(p, np.uint32), _arr(q, np.uint32)
+    roots = (cuboid_root * max(1, cap))()
+    n = ctypes.c_uint64(0)
+    st = _load().cuboid_root_check(ctx, _p(p, u32), _p(q, u32), len(p), roots, int(cap),
+                                   ctypes.byref(n))
+    _check(st, "cuboid_root_check", needed=n.value if st == E_CAPACITY else None)
+    return [(r.p, r.q, r.t, r.flags, r.input_index) for r in roots[:n.value]]
+
+
+def cuboid_exact_check(p, q, t):
+    z, f = i32(0), u32(0)
+    _check(_load().cuboid_exact_check(int(p), int(q), int(t), ctypes.byref(z), ctypes.byref(f)),
+           "cuboid_exact_check")
+    return bool(z.value), f.value
+
+
+def cuboid_exact_value(p, q, t):
+    buf = ctypes.create_string_buffer(1024)
+    _check(_load().cuboid_exact_value(int(p), int(q), int(t), buf, 1024), "cuboid_exact_value")
+    return int(buf.value.decode())
+
+
+def cuboid_canonical_primes(primes):
+    pr = _arr(primes, np.uint32)
+    out = np.zeros(max(1, len(pr)), dtype=np.uint32)
+    triv = np.zeros(max(1, len(pr)), dtype=np.uint8)
+    _check(_load().cuboid_canonical_primes(_p(pr, u32), len(pr), _p(out, u32), _p(triv, u8)),
+           "cuboid_canonical_primes")
+    return out[:len(pr)], triv[:len(pr)].astype(bool)
+
+
+def cuboid_sieve_batch(ctx, requests, primes, caps=1024, stream=None):
+    """requests: list of (p0, p1, q0, q1).  Returns (status, [dict per request])."""
+    pr = _arr(primes, np.uint32)
+    n = len(requests)
+    if isinstance(caps, int):
+        caps = [caps] * n
+    req = (cuboid_request * max(1, n))()
+    res = (cuboid_result * max(1, n))()
+    keep = []
+    for i, (a, b, c, d) in enumerate(requests):
+        req[i].p0, req[i].p1, req[i].q0, req[i].q1 = int(a), int(b), int(c), int(d)
+        sv = np.zeros(max(1, caps[i]), dtype=np.uint64)
+        ct = np.zeros(max(1, len(pr)), dtype=np.uint64)
+        keep.append((sv, ct))
+        res[i].survivors = _p(sv, u64)
+        res[i].cap = int(caps[i])
+        res[i].counts = _p(ct, u64)
+    st = _load().cuboid_sieve_batch(ctx, req, n, _p(pr, u32), len(pr), res, _stream(stream))
+    if st not in (OK, E_CAPACITY, E_LIMIT):
+        _check(st, "cuboid_sieve_batch")
+    out = []
+    for i in range(n):
+        sv, ct = keep[i]
+        ns = res[i].n_survivors
+        out.append(dict(status=res[i].status, counts=ct[:len(pr)].copy(), n_pairs=res[i].n_pairs,
+                        n_survivors=ns,
+                        survivors=sv[:ns].copy() if res[i].status == OK else None))
+    return st, out
+
+
+def cuboid_enable_timing(ctx, on=True):
+    _check(_load().cuboid_enable_timing(ctx, 1 if on else 0), "cuboid_enable_timing")
+
+
+def cuboid_last_timing(ctx):
+    t = cuboid_timing()
+    _check(_load().cuboid_last_timing(ctx, ctypes.byref(t)), "cuboid_last_timing")
+    return dict(sweep_ms=t.sweep_ms, total_gpu_ms=t.total_gpu_ms, units=t.units,
+                dense_primes=t.dense_primes, workgroups=t.workgroups)
+
+
+def cuboid_set_tuning(ctx, primes, dense_primes=None, workgroups=0, lds_budget=0):
+    pr = _arr(primes, np.uint32)
+    if dense_primes is None and not workgroups and not lds_budget:
+        _check(_load().cuboid_set_tuning(ctx, _p(pr, u32), len(pr), None), "cuboid_set_tuning")
+        return
+    t = cuboid_tuning(0xffffffff if dense_primes is None else int(dense_primes), int(workgroups),
+                      int(lds_budget), 0)
+    _check(_load().cuboid_set_tuning(ctx, _p(pr, u32), len(pr), ctypes.byref(t)),
+           "cuboid_set_tuning")
+
+
+def cuboid_get_tuning(ctx, primes):
+    pr = _arr(primes, np.uint32)
+    t = cuboid_tuning()
+    _check(_load().cuboid_get_tuning(ctx, _p(pr, u32), len(pr), ctypes.byref(t)),
+           "cuboid_get_tuning")
+    return dict(dense_primes=t.dense_primes, workgroups=t.workgroups, lds_budget=t.lds_budget)
+
+
+def cuboid_autotune(ctx, primes, cache_path=None):
+    pr = _arr(primes, np.uint32)
+    t = cuboid_tuning()
+    cp = cache_path.encode() if cache_path else None
+    _check(_load().cuboid_autotune(ctx, _p(pr, u32), len(pr), cp, ctypes.byref(t)),
+           "cuboid_autotune")
+    return dict(dense_primes=t.dense_primes, workgroups=t.workgroups, lds_budget=t.lds_budget)
+
+
+class Context:
+    """Owns one cuboid_ctx; methods are the functions above without `ctx`."""
+
+    def __init__(self, device=0):
+        self.handle = cuboid_create(device)
+
+    def close(self):
+        if self.handle is not None:
+            st = cuboid_destroy(self.handle)
+            _check(st, "cuboid_destroy")
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __getattr__(self, name):
+        fn = globals().get("cuboid_" + name)
+        if fn is None:
+            raise AttributeError(name)
+        return lambda *a, **k: fn(self.handle, *a, **k)

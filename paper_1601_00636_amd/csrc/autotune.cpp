@@ -1,0 +1,133 @@
+// Autotuner: times the sweep for candidate tunings (number of dense primes K,
+// persistent grid size) on a sample rectangle and keeps the fastest for the
+// prime set.  Choices are cached as JSON lines keyed by device architecture
+// and prime set.  Results never depend on the tuning (the dense primes are an
+// ascending prefix and every count is the first rejecting prime).
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+
+#include "runtime.h"
+
+using namespace cuboid;
+
+namespace {
+
+std::string prime_key(const std::vector<uint32_t> &primes) {
+    // FNV-1a over the sorted list, plus its length and ends for readability
+    uint64_t h = 1469598103934665603ull;
+    for (uint32_t r : primes) {
+        for (int b = 0; b < 4; ++b) {
+            h ^= (r >> (8 * b)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    }
+    char buf[96];
+    snprintf(buf, sizeof(buf), "n%zu_%u_%u_%016llx", primes.size(), primes.front(), primes.back(),
+             (unsigned long long)h);
+    return buf;
+}
+
+bool read_cache(const char *path, const std::string &arch, const std::string &key,
+                cuboid_tuning *out) {
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (fgets(line, sizeof(line), f)) {
+        if (!strstr(line, ("\"arch\": \"" + arch + "\"").c_str())) continue;
+        if (!strstr(line, ("\"primes\": \"" + key + "\"").c_str())) continue;
+        unsigned k = 0, w = 0, b = 0;
+        const char *pk = strstr(line, "\"dense_primes\": ");
+        const char *pw = strstr(line, "\"workgroups\": ");
+        const char *pb = strstr(line, "\"lds_budget\": ");
+        if (!pk || !pw || !pb) continue;
+        if (sscanf(pk, "\"dense_primes\": %u", &k) != 1) continue;
+        if (sscanf(pw, "\"workgroups\": %u", &w) != 1) continue;
+        if (sscanf(pb, "\"lds_budget\": %u", &b) != 1) continue;
+        out->dense_primes = k;
+        out->workgroups = w;
+        out->lds_budget = b;
+        out->reserved = 0;
+        found = true;   // the last matching line wins
+    }
+    fclose(f);
+    return found;
+}
+
+void append_cache(const char *path, const std::string &arch, const std::string &key,
+                  const cuboid_tuning &t, double ms) {
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f,
+            "{\"arch\": \"%s\", \"primes\": \"%s\", \"dense_primes\": %u, \"workgroups\": %u, "
+            "\"lds_budget\": %u, \"sample_ms\": %.4f}\n",
+            arch.c_str(), key.c_str(), t.dense_primes, t.workgroups, t.lds_budget, ms);
+    fclose(f);
+}
+
+}  // namespace
+
+extern "C" int cuboid_autotune(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes,
+                               const char *cache_path, cuboid_tuning *out) {
+    if (!ctx) return CUBOID_E_NOT_LOADED;
+    std::vector<uint32_t> sorted;
+    int st = canonical_primes(primes, n_primes, &sorted);
+    if (st) return st;
+    std::lock_guard<std::recursive_mutex> g(ctx->mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) return CUBOID_E_DEVICE;
+    const std::string arch(ctx->arch), key = prime_key(sorted);
+    cuboid_tuning best;
+    if (cache_path && read_cache(cache_path, arch, key, &best)) {
+        ctx->tunings[sorted] = best;
+        if (out) *out = best;
+        return CUBOID_OK;
+    }
+    Plan *pl = nullptr;
+    st = build_plan(ctx, sorted, &pl);
+    if (st) return st;
+    const uint32_t budget = (uint32_t)std::min<size_t>(ctx->max_lds - kSweepFixedLds, 96 * 1024);
+    const uint32_t kmax = default_dense(*pl, budget);
+    const uint32_t cus = (uint32_t)ctx->cu_count;
+    // sample: 8192 rows x 65536 columns near 2^19, the scale of the batched workloads
+    std::vector<cuboid_request> rect(1);
+    rect[0].p0 = 1u << 19; rect[0].p1 = (1u << 19) + 8191;
+    rect[0].q0 = 1u << 19; rect[0].q1 = (1u << 19) + 65535;
+    const bool saved_timing = ctx->timing;
+    ctx->timing = true;
+    double best_ms = 1e30;
+    best.dense_primes = 0; best.workgroups = 2 * cus; best.lds_budget = budget; best.reserved = 0;
+    const uint32_t klo = kmax > 5 ? kmax - 5 : 0;
+    const uint32_t wgs[4] = {cus, 2 * cus, 4 * cus, 8 * cus};
+    for (uint32_t K = klo; K <= kmax; ++K) {
+        for (uint32_t w : wgs) {
+            cuboid_tuning t;
+            t.dense_primes = K; t.workgroups = w; t.lds_budget = budget; t.reserved = 0;
+            ctx->tunings[sorted] = t;
+            double ms_best = 1e30;
+            for (int rep = 0; rep < 3; ++rep) {
+                std::vector<std::vector<uint64_t>> cnt;
+                std::vector<uint64_t> pairs;
+                std::vector<SurvEntry> surv;
+                uint64_t ns = 0;
+                st = sieve_rects(ctx, sorted, rect, 1 << 16, ctx->stream, &cnt, &pairs, &surv, &ns);
+                if (st) break;
+                ms_best = std::min(ms_best, ctx->last.sweep_ms);
+            }
+            if (st) break;
+            if (ms_best < best_ms) { best_ms = ms_best; best = t; }
+        }
+        if (st) break;
+    }
+    ctx->timing = saved_timing;
+    if (st) {
+        ctx->tunings.erase(sorted);
+        return st;
+    }
+    ctx->tunings[sorted] = best;
+    if (cache_path) append_cache(cache_path, arch, key, best, best_ms);
+    if (out) *out = best;
+    return CUBOID_OK;
+}

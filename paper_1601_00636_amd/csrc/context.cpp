@@ -1,0 +1,485 @@
+// Host runtime of libcuboid: context, resident tables, prime plans, the plain
+// and batched sieve entry points and the root check.  Every arithmetic step of
+// the sieve runs in the HIP kernels; this file validates arguments, plans the
+// launch (unit space, rows, tables) and moves results.
+#include "runtime.h"
+
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <numeric>
+
+#include "bigint.h"
+
+using namespace cuboid;
+
+namespace cuboid {
+
+const char *status_text(int s) {
+    switch (s) {
+        case CUBOID_OK: return "ok";
+        case CUBOID_E_BUSY: return "busy: work in flight";
+        case CUBOID_E_RANGE: return "invalid range";
+        case CUBOID_E_LIMIT: return "size limit exceeded";
+        case CUBOID_E_PRIMES: return "invalid prime list";
+        case CUBOID_E_CAPACITY: return "output capacity too small";
+        case CUBOID_E_NOT_LOADED: return "context not loaded";
+        case CUBOID_E_DEVICE: return "device or HIP runtime error";
+        case CUBOID_E_ARG: return "invalid argument";
+        default: return "unknown status";
+    }
+}
+
+bool is_prime_u32(uint32_t x) {
+    if (x < 2) return false;
+    for (uint32_t d = 2; (uint64_t)d * d <= x; ++d)
+        if (x % d == 0) return false;
+    return true;
+}
+
+int canonical_primes(const uint32_t *primes, uint32_t n, std::vector<uint32_t> *sorted) {
+    if (!primes || n == 0) return CUBOID_E_PRIMES;
+    if (n > kMaxPrimes) return CUBOID_E_PRIMES;
+    sorted->assign(primes, primes + n);
+    std::sort(sorted->begin(), sorted->end());
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint32_t r = (*sorted)[i];
+        if (r >= 65536 || !is_prime_u32(r)) return CUBOID_E_PRIMES;
+        if (i && (*sorted)[i - 1] == r) return CUBOID_E_PRIMES;
+    }
+    return CUBOID_OK;
+}
+
+hipError_t DevBuf::ensure(size_t n) {
+    if (n <= bytes && p) return hipSuccess;
+    release();
+    size_t want = n ? n : 1;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) { p = nullptr; bytes = 0; return e; }
+    bytes = want;
+    return hipSuccess;
+}
+
+void DevBuf::release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+hipError_t HostBuf::ensure(size_t n) {
+    if (n <= bytes && p) return hipSuccess;
+    release();
+    size_t want = n ? n : 1;
+    hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+    if (e != hipSuccess) { p = nullptr; bytes = 0; return e; }
+    bytes = want;
+    return hipSuccess;
+}
+
+void HostBuf::release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+}  // namespace cuboid
+
+#define HIPCHK(expr)                                  \
+    do {                                              \
+        hipError_t _e = (expr);                       \
+        if (_e != hipSuccess) return CUBOID_E_DEVICE; \
+    } while (0)
+
+namespace {
+
+uint32_t magic_of(uint32_t r) { return (uint32_t)(0x100000000ull / r); }
+
+hipStream_t pick_stream(cuboid_ctx *ctx, void *s) {
+    return s ? (hipStream_t)s : ctx->stream;
+}
+
+template <typename T>
+hipError_t upload(DevBuf &b, const std::vector<T> &v, hipStream_t s) {
+    hipError_t e = b.ensure(v.size() * sizeof(T));
+    if (e != hipSuccess || v.empty()) return e;
+    return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+std::vector<uint64_t> prefix_of(const std::vector<uint64_t> &w) {
+    std::vector<uint64_t> pre(w.size() + 1, 0);
+    for (size_t i = 0; i < w.size(); ++i) pre[i + 1] = pre[i] + w[i];
+    return pre;
+}
+
+}  // namespace
+
+namespace cuboid {
+
+// Ratio vectors and inverse tables for every prime of the set, built on the
+// GPU; the per-prime count of unsolvable ratio classes tells which tables are
+// identically zero.
+int build_plan(cuboid_ctx *ctx, const std::vector<uint32_t> &primes, Plan **out) {
+    auto it = ctx->plans.find(primes);
+    if (it != ctx->plans.end()) { *out = it->second.get(); return CUBOID_OK; }
+    std::unique_ptr<Plan> pl(new Plan());
+    pl->primes = primes;
+    const uint32_t n = (uint32_t)primes.size();
+    hipStream_t s = ctx->stream;
+    std::vector<uint32_t> voff(n), ioff(n);
+    std::vector<uint64_t> wv(n), wi(n);
+    uint64_t tot = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        voff[i] = (uint32_t)tot;
+        ioff[i] = (uint32_t)tot;
+        tot += primes[i];
+        wv[i] = primes[i] == 2 ? 1 : (primes[i] - 1) / 2;
+        wi[i] = primes[i] - 1;
+    }
+    pl->voff = voff;
+    pl->ioff = ioff;
+    const std::vector<uint64_t> pv = prefix_of(wv), pi = prefix_of(wi);
+    DevBuf d_pr, d_voff, d_ioff, d_pv, d_pi, d_pop;
+    HIPCHK(upload(d_pr, primes, s));
+    HIPCHK(upload(d_voff, voff, s));
+    HIPCHK(upload(d_ioff, ioff, s));
+    HIPCHK(upload(d_pv, pv, s));
+    HIPCHK(upload(d_pi, pi, s));
+    HIPCHK(pl->vpool.ensure(tot));
+    HIPCHK(pl->ipool.ensure(tot * 2));
+    HIPCHK(launch_fill_u8((uint8_t *)pl->vpool.p, tot, 0, s));
+    HIPCHK(launch_fill_u8((uint8_t *)pl->ipool.p, tot * 2, 0, s));
+    HIPCHK(launch_ratio_vectors((const uint32_t *)d_pr.p, (const uint32_t *)d_voff.p, n,
+                                (const uint64_t *)d_pv.p, pv[n], (uint8_t *)pl->vpool.p, s));
+    HIPCHK(launch_inverse_tables((const uint32_t *)d_pr.p, (const uint32_t *)d_ioff.p, n,
+                                 (const uint64_t *)d_pi.p, pi[n], (uint16_t *)pl->ipool.p, s));
+    HIPCHK(d_pop.ensure(n * 4));
+    HIPCHK(launch_vector_popcount((const uint32_t *)d_pr.p, (const uint32_t *)d_voff.p, n,
+                                  (const uint8_t *)pl->vpool.p, (uint32_t *)d_pop.p, s));
+    std::vector<uint32_t> pop(n);
+    HIPCHK(hipMemcpyAsync(pop.data(), d_pop.p, n * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    pl->unsolvable_classes = pop;
+    pl->trivial.resize(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        pl->trivial[i] = pop[i] == 0;
+        if (!pl->trivial[i]) pl->nontriv_idx.push_back(i);
+    }
+    *out = pl.get();
+    ctx->plans[primes] = std::move(pl);
+    return CUBOID_OK;
+}
+
+uint32_t default_dense(const Plan &pl, uint32_t lds_budget) {
+    uint64_t bytes = 0;
+    uint32_t k = 0;
+    while (k < pl.nontriv_idx.size() && k < (uint32_t)kKMax) {
+        const uint64_t r = pl.primes[pl.nontriv_idx[k]];
+        if (bytes + 8 * r * r > lds_budget) break;
+        bytes += 8 * r * r;
+        ++k;
+    }
+    return k;
+}
+
+// Window tables for the first K non-trivial primes and the deep-prime list.
+int build_dense(cuboid_ctx *ctx, Plan *pl, uint32_t K, DenseSet **out) {
+    auto it = pl->dense.find(K);
+    if (it != pl->dense.end()) { *out = it->second.get(); return CUBOID_OK; }
+    if (K > pl->nontriv_idx.size() || K > (uint32_t)kKMax) return CUBOID_E_ARG;
+    std::unique_ptr<DenseSet> ds(new DenseSet());
+    hipStream_t s = ctx->stream;
+    ds->K = K;
+    std::vector<uint32_t> pr(K), vo(K), io(K), wo(K);
+    std::vector<uint64_t> work(K);
+    uint64_t words = 0;
+    for (uint32_t k = 0; k < K; ++k) {
+        const uint32_t i = pl->nontriv_idx[k];
+        const uint32_t r = pl->primes[i];
+        pr[k] = r; vo[k] = pl->voff[i]; io[k] = pl->ioff[i]; wo[k] = (uint32_t)words;
+        work[k] = (uint64_t)r * r;
+        ds->dr[k] = r;
+        ds->dm[k] = magic_of(r);
+        ds->dstep[k] = 64 % r;
+        ds->doff[k] = (uint32_t)(words * 8);
+        words += (uint64_t)r * r;
+    }
+    ds->words = (uint32_t)words;
+    HIPCHK(ds->tab.ensure(words * 8));
+    if (K) {
+        const std::vector<uint64_t> pre = prefix_of(work);
+        DevBuf d_pr, d_vo, d_io, d_wo, d_pre;
+        HIPCHK(upload(d_pr, pr, s));
+        HIPCHK(upload(d_vo, vo, s));
+        HIPCHK(upload(d_io, io, s));
+        HIPCHK(upload(d_wo, wo, s));
+        HIPCHK(upload(d_pre, pre, s));
+        HIPCHK(launch_dense_windows((const uint32_t *)d_pr.p, (const uint32_t *)d_vo.p,
+                                    (const uint32_t *)d_io.p, (const uint32_t *)d_wo.p, K,
+                                    (const uint64_t *)d_pre.p, pre[K], (const uint8_t *)pl->vpool.p,
+                                    (const uint16_t *)pl->ipool.p, (uint64_t *)ds->tab.p, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    std::vector<DeepPrime> deep;
+    for (size_t k = K; k < pl->nontriv_idx.size(); ++k) {
+        const uint32_t i = pl->nontriv_idx[k];
+        DeepPrime d;
+        d.r = pl->primes[i];
+        d.m = magic_of(d.r);
+        d.voff = pl->voff[i];
+        d.ioff = pl->ioff[i];
+        deep.push_back(d);
+    }
+    ds->n_deep = (uint32_t)deep.size();
+    HIPCHK(upload(ds->deep, deep, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *out = ds.get();
+    pl->dense[K] = std::move(ds);
+    return CUBOID_OK;
+}
+
+// Resident row table for 1 <= p <= R, grown to cover p_max when p_max <= 2^24.
+int ensure_rows(cuboid_ctx *ctx, uint32_t p_max) {
+    if (p_max <= ctx->rows_R) return CUBOID_OK;
+    if (p_max > kResidentRowsMax) return CUBOID_E_LIMIT;
+    uint64_t R = 1u << 16;
+    while (R < p_max) R <<= 1;
+    if (R > kResidentRowsMax) R = kResidentRowsMax;
+    HIPCHK(ctx->rows.ensure(R * sizeof(RowInfo)));
+    HIPCHK(launch_row_info((const uint32_t *)ctx->primes16.p, (const uint32_t *)ctx->magic16.p,
+                           ctx->n16, 1, R, (RowInfo *)ctx->rows.p, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->rows_R = (uint32_t)R;
+    return CUBOID_OK;
+}
+
+cuboid_tuning tuning_for(cuboid_ctx *ctx, const std::vector<uint32_t> &primes, const Plan &pl) {
+    cuboid_tuning t;
+    auto it = ctx->tunings.find(primes);
+    if (it != ctx->tunings.end()) t = it->second;
+    else { t.dense_primes = 0xffffffffu; t.workgroups = 0; t.lds_budget = kDefaultLdsBudget; t.reserved = 0; }
+    if (t.lds_budget == 0) t.lds_budget = kDefaultLdsBudget;
+    const uint32_t kmax = default_dense(pl, t.lds_budget);
+    if (t.dense_primes > kmax) t.dense_primes = kmax;
+    if (t.workgroups == 0) t.workgroups = 2 * ctx->cu_count;
+    return t;
+}
+
+// One sweep launch over `reqs` (already holding row pointers), accumulating
+// into the context's count / pair / survivor buffers (zeroed by the caller).
+// Request j of this launch uses counter slot slot0 + j and survivor request
+// number slot0 + j.
+int launch_reqs(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid_tuning &tun,
+                std::vector<ReqDesc> &reqs, uint32_t slot0, uint64_t surv_cap, hipStream_t s,
+                uint64_t *units_out) {
+    uint64_t units = 0;
+    for (auto &r : reqs) {
+        r.nrb = (uint32_t)(((uint64_t)r.p1 - r.p0 + 64) / 64);
+        r.nwin = (uint32_t)(((uint64_t)r.q1 - r.q0 + 64) / 64);
+        r.unit0 = units;
+        units += (uint64_t)r.nrb * r.nwin;
+    }
+    // staged through pinned memory; the previous user of the staging buffer
+    // on this stream has completed once the stream is idle
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(ctx->req_stage.ensure(reqs.size() * sizeof(ReqDesc)));
+    memcpy(ctx->req_stage.p, reqs.data(), reqs.size() * sizeof(ReqDesc));
+    HIPCHK(ctx->reqbuf.ensure(reqs.size() * sizeof(ReqDesc)));
+    HIPCHK(hipMemcpyAsync(ctx->reqbuf.p, ctx->req_stage.p, reqs.size() * sizeof(ReqDesc),
+                          hipMemcpyHostToDevice, s));
+    SweepParams P;
+    memset(&P, 0, sizeof(P));
+    P.K = ds.K;
+    for (uint32_t k = 0; k < ds.K; ++k) {
+        P.dr[k] = ds.dr[k]; P.dm[k] = ds.dm[k]; P.dstep[k] = ds.dstep[k]; P.doff[k] = ds.doff[k];
+    }
+    P.dense_words = ds.words;
+    P.dense_tab = (const uint64_t *)ds.tab.p;
+    P.wheel = (const uint64_t *)ctx->wheel.p;
+    P.n_deep = ds.n_deep;
+    P.nc = ds.K + ds.n_deep;
+    P.deep = (const DeepPrime *)ds.deep.p;
+    P.vpool = (const uint8_t *)pl.vpool.p;
+    P.ipool = (const uint16_t *)pl.ipool.p;
+    P.req = (const ReqDesc *)ctx->reqbuf.p;
+    P.n_req = (uint32_t)reqs.size();
+    P.req_base = slot0;
+    P.n_units = units;
+    P.counts = (unsigned long long *)ctx->counts.p + (uint64_t)slot0 * P.nc;
+    P.pairs = (unsigned long long *)ctx->pairs.p + slot0;
+    P.surv = (SurvEntry *)ctx->surv.p;
+    P.surv_cap = surv_cap;
+    P.surv_n = (unsigned long long *)ctx->surv_n.p;
+    const size_t lds = (size_t)ds.words * 8 + kSweepFixedLds;
+    if (lds > ctx->max_lds) return CUBOID_E_LIMIT;
+    if (ctx->timing) HIPCHK(hipEventRecord(ctx->ev_sweep0, s));
+    HIPCHK(launch_sweep(P, (int)tun.workgroups, lds, s));
+    if (ctx->timing) HIPCHK(hipEventRecord(ctx->ev_sweep1, s));
+    *units_out = units;
+    return CUBOID_OK;
+}
+
+int ensure_scratch(cuboid_ctx *ctx, uint32_t n_req, uint32_t nc, uint64_t surv_cap) {
+    HIPCHK(ctx->counts.ensure((size_t)n_req * nc * 8 + 8));
+    HIPCHK(ctx->pairs.ensure((size_t)n_req * 8 + 8));
+    HIPCHK(ctx->surv_n.ensure(8));
+    const uint64_t rounded = (surv_cap + 1023) / 1024 * 1024;
+    HIPCHK(ctx->surv.ensure(rounded * sizeof(SurvEntry) + sizeof(SurvEntry)));
+    HIPCHK(ctx->surv_tmp.ensure(rounded * sizeof(SurvEntry) + sizeof(SurvEntry)));
+    return CUBOID_OK;
+}
+
+int zero_scratch(cuboid_ctx *ctx, uint32_t n_req, uint32_t nc, hipStream_t s) {
+    HIPCHK(launch_fill_u64((uint64_t *)ctx->counts.p, (uint64_t)n_req * nc, 0, s));
+    HIPCHK(launch_fill_u64((uint64_t *)ctx->pairs.p, n_req, 0, s));
+    HIPCHK(launch_fill_u64((uint64_t *)ctx->surv_n.p, 1, 0, s));
+    return CUBOID_OK;
+}
+
+// Sorted survivor entries (n of them, n <= scratch) to host.
+int fetch_survivors(cuboid_ctx *ctx, uint64_t n, std::vector<SurvEntry> *out, hipStream_t s) {
+    out->resize(n);
+    if (!n) return CUBOID_OK;
+    SurvEntry *sorted = nullptr;
+    HIPCHK(launch_sort_surv((SurvEntry *)ctx->surv.p, (SurvEntry *)ctx->surv_tmp.p,
+                            (const unsigned long long *)ctx->surv_n.p, n, &sorted, s));
+    HIPCHK(hipMemcpyAsync(out->data(), sorted, n * sizeof(SurvEntry), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return CUBOID_OK;
+}
+
+// Map canonical non-trivial counts to the caller's prime order.
+void map_counts(const Plan &pl, const std::vector<uint32_t> &caller, const uint64_t *canon,
+                uint64_t *out) {
+    // rank of each non-trivial prime in canonical order
+    for (size_t i = 0; i < caller.size(); ++i) {
+        const uint32_t r = caller[i];
+        const size_t pos = std::lower_bound(pl.primes.begin(), pl.primes.end(), r) - pl.primes.begin();
+        if (pl.trivial[pos]) { out[i] = 0; continue; }
+        const size_t k = std::lower_bound(pl.nontriv_idx.begin(), pl.nontriv_idx.end(), (uint32_t)pos) -
+                         pl.nontriv_idx.begin();
+        out[i] = canon[k];
+    }
+}
+
+int rect_valid(uint32_t p0, uint32_t p1, uint32_t q0, uint32_t q1) {
+    if (p0 == 0 || q0 == 0 || p0 > p1 || q0 > q1) return CUBOID_E_RANGE;
+    return CUBOID_OK;
+}
+
+// The plain and batched sieve share this path.  `rects` are validated.
+int sieve_rects(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes,
+                const std::vector<cuboid_request> &rects, uint64_t surv_cap_total,
+                hipStream_t s, std::vector<std::vector<uint64_t>> *counts_out,
+                std::vector<uint64_t> *pairs_out, std::vector<SurvEntry> *surv_out,
+                uint64_t *n_surv_out) {
+    std::vector<uint32_t> primes;
+    int st = canonical_primes(caller_primes.data(), (uint32_t)caller_primes.size(), &primes);
+    if (st) return st;
+    Plan *pl = nullptr;
+    st = build_plan(ctx, primes, &pl);
+    if (st) return st;
+    const cuboid_tuning tun = tuning_for(ctx, primes, *pl);
+    DenseSet *ds = nullptr;
+    st = build_dense(ctx, pl, tun.dense_primes, &ds);
+    if (st) return st;
+    const uint32_t nc = ds->K + ds->n_deep;
+    const uint32_t n_req = (uint32_t)rects.size();
+    const uint64_t surv_cap = std::min<uint64_t>(surv_cap_total, kMaxSurvScratch);
+    st = ensure_scratch(ctx, n_req, nc, surv_cap);
+    if (st) return st;
+
+    // rows: resident table when every row fits below 2^24, else per-band scratch
+    uint32_t pmax = 0;
+    for (auto &r : rects) pmax = std::max(pmax, r.p1);
+    const bool resident = pmax <= kResidentRowsMax;
+    if (resident) {
+        st = ensure_rows(ctx, pmax);
+        if (st) return st;
+    }
+    if (ctx->timing) HIPCHK(hipEventRecord(ctx->ev_total0, s));
+    st = zero_scratch(ctx, n_req, nc, s);
+    if (st) return st;
+    uint64_t units_total = 0;
+    double sweep_ms = 0;
+    if (resident) {
+        std::vector<ReqDesc> reqs(n_req);
+        for (uint32_t i = 0; i < n_req; ++i) {
+            ReqDesc &d = reqs[i];
+            memset(&d, 0, sizeof(d));
+            d.p0 = rects[i].p0; d.p1 = rects[i].p1; d.q0 = rects[i].q0; d.q1 = rects[i].q1;
+            d.rows = (const RowInfo *)ctx->rows.p;
+            d.rows_p0 = 1;
+            d.ip0 = rects[i].p0;
+        }
+        st = launch_reqs(ctx, *pl, *ds, tun, reqs, 0, surv_cap, s, &units_total);
+        if (st) return st;
+        if (ctx->timing) {
+            HIPCHK(hipEventSynchronize(ctx->ev_sweep1));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, ctx->ev_sweep0, ctx->ev_sweep1));
+            sweep_ms += ms;
+        }
+    } else {
+        // bands of rows with their factors computed per band; one request at
+        // a time, each band keeping the request's number for its counters
+        for (uint32_t i = 0; i < n_req; ++i) {
+            const cuboid_request &rc = rects[i];
+            for (uint64_t b0 = rc.p0; b0 <= rc.p1; b0 += kBandRows) {
+                const uint64_t b1 = std::min<uint64_t>(rc.p1, b0 + kBandRows - 1);
+                HIPCHK(ctx->band_rows.ensure((b1 - b0 + 1) * sizeof(RowInfo)));
+                HIPCHK(launch_row_info((const uint32_t *)ctx->primes16.p,
+                                       (const uint32_t *)ctx->magic16.p, ctx->n16, (uint32_t)b0,
+                                       b1 - b0 + 1, (RowInfo *)ctx->band_rows.p, s));
+                std::vector<ReqDesc> reqs(1);
+                ReqDesc &d = reqs[0];
+                memset(&d, 0, sizeof(d));
+                d.p0 = (uint32_t)b0; d.p1 = (uint32_t)b1; d.q0 = rc.q0; d.q1 = rc.q1;
+                d.rows = (const RowInfo *)ctx->band_rows.p;
+                d.rows_p0 = (uint32_t)b0;
+                d.ip0 = rc.p0;
+                uint64_t units = 0;
+                st = launch_reqs(ctx, *pl, *ds, tun, reqs, i, surv_cap, s, &units);
+                if (st) return st;
+                units_total += units;
+                if (ctx->timing) {
+                    HIPCHK(hipEventSynchronize(ctx->ev_sweep1));
+                    float ms = 0;
+                    HIPCHK(hipEventElapsedTime(&ms, ctx->ev_sweep0, ctx->ev_sweep1));
+                    sweep_ms += ms;
+                }
+            }
+        }
+    }
+    std::vector<uint64_t> canon((size_t)n_req * nc), pairs(n_req);
+    uint64_t nsurv = 0;
+    HIPCHK(hipMemcpyAsync(canon.data(), ctx->counts.p, canon.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(pairs.data(), ctx->pairs.p, pairs.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&nsurv, ctx->surv_n.p, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *n_surv_out = nsurv;
+    counts_out->assign(n_req, std::vector<uint64_t>(caller_primes.size(), 0));
+    for (uint32_t i = 0; i < n_req; ++i)
+        map_counts(*pl, caller_primes, canon.data() + (size_t)i * nc, (*counts_out)[i].data());
+    *pairs_out = pairs;
+    surv_out->clear();
+    if (nsurv > 0 && nsurv <= surv_cap) {
+        st = fetch_survivors(ctx, nsurv, surv_out, s);
+        if (st) return st;
+    }
+    if (ctx->timing) {
+        HIPCHK(hipEventRecord(ctx->ev_total1, s));
+        HIPCHK(hipEventSynchronize(ctx->ev_total1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, ctx->ev_total0, ctx->ev_total1));
+        ctx->last.sweep_ms = sweep_ms;
+        ctx->last.total_gpu_ms = ms;
+        ctx->last.units = units_total;
+        ctx->last.dense_primes = ds->K;
+        ctx->last.workgroups = tun.workgroups;
+    }
+    if (nsurv > surv_cap && surv_cap < surv_cap_total) return CUBOID_E_LIMIT;
+    return CUBOID_OK;
+}
+
+}  // namespace cuboid

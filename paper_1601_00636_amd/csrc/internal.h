@@ -1,0 +1,136 @@
+// Internal declarations shared by the host runtime and the HIP kernels of
+// libcuboid.  Not part of the public interface (see include/cuboid.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cuboid {
+
+constexpr int kWave = 64;            // CDNA wavefront width
+constexpr int kWavesPerWG = 8;       // sweep workgroup = 512 lanes
+constexpr int kKMax = 12;            // most dense (bit-window) primes per launch
+constexpr int kMaxBigFactors = 7;    // distinct primes >= 11 of a uint32 (11*13*..*31 < 2^32 < that*37)
+constexpr int kQueueCap = 128;       // per-wave queue of windows that outlive the dense primes
+constexpr int kDeepCounters = 128;   // per-wave LDS counters for the first deep primes
+constexpr int kWheel = 210;          // 2*3*5*7
+constexpr int kWheelSubsets = 16;    // subsets of {2,3,5,7}
+
+// Distinct prime factors of one row coordinate p.
+//   meta bits 0..3: which of 2, 3, 5, 7 divide p; bits 4..7: number of f[] used.
+//   f[]: the distinct prime factors >= 11 of p, ascending.
+struct RowInfo {
+    uint32_t meta;
+    uint32_t f[kMaxBigFactors];
+};
+
+// One prime tested after the dense phase ("deep" prime).  Its table is kept in
+// ratio form: u_r(a, b) = v[a * b^-1 mod r] for a, b != 0, and 0 otherwise.
+struct DeepPrime {
+    uint32_t r;       // the prime
+    uint32_t m;       // floor(2^32 / r), for x mod r by multiply-high
+    uint32_t voff;    // byte offset of its ratio vector in the vector pool
+    uint32_t ioff;    // element offset of its inverse table in the inverse pool
+};
+
+// One rectangle of a launch, with its place in the flattened unit space.
+// A unit is one wavefront step: 64 consecutive rows x 64 consecutive columns.
+struct ReqDesc {
+    uint32_t p0, p1, q0, q1;
+    uint32_t nrb;          // ceil(rows / 64)
+    uint32_t nwin;         // ceil(cols / 64)
+    uint64_t unit0;        // first unit of this request in the flattened order
+    const RowInfo *rows;   // row info for p at rows[p - rows_p0]
+    uint32_t rows_p0;
+    uint32_t ip0;          // p0 of the caller's rectangle (survivor indices)
+};
+
+struct SurvEntry {
+    uint64_t idx;          // (p - p0) * (q1 - q0 + 1) + (q - q0)
+    uint32_t req;          // request number within the launch
+    uint32_t pad;
+};
+
+struct SweepParams {
+    uint32_t K;                          // dense primes in this launch
+    uint32_t dr[kKMax];                  // dense prime r
+    uint32_t dm[kKMax];                  // floor(2^32 / r)
+    uint32_t dstep[kKMax];               // 64 mod r
+    uint32_t doff[kKMax];                // LDS byte offset of that prime's window table
+    uint32_t dense_words;                // 64-bit words of all window tables
+    const uint64_t *dense_tab;           // window tables in HBM (copied to LDS)
+    const uint64_t *wheel;               // 16 x 210 coprimality windows (copied to LDS)
+    uint32_t n_deep;
+    uint32_t nc;                         // counters per request = K + n_deep
+    const DeepPrime *deep;
+    const uint8_t *vpool;                // ratio vectors
+    const uint16_t *ipool;               // inverse tables
+    const ReqDesc *req;
+    uint32_t n_req;
+    uint32_t req_base;                   // added to request numbers in survivor entries
+    uint64_t n_units;
+    unsigned long long *counts;          // [n_req][nc], canonical ascending order
+    unsigned long long *pairs;           // [n_req]
+    SurvEntry *surv;
+    unsigned long long surv_cap;
+    unsigned long long *surv_n;
+};
+
+// LDS bytes the sweep needs beyond the dense tables.
+constexpr size_t kWheelBytes = (size_t)kWheelSubsets * kWheel * 8;
+constexpr size_t kQueueEntryBytes = 16;
+constexpr size_t kPerWaveBytes = kQueueCap * kQueueEntryBytes + kDeepCounters * 4;
+constexpr size_t kSweepFixedLds = kWheelBytes + kWavesPerWG * kPerWaveBytes;
+
+// ---- kernel launchers (kernels_*.hip) ----
+hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t *p, uint64_t n, uint8_t v, hipStream_t s);
+hipError_t launch_q_eval(const uint32_t *p, const uint32_t *q, const uint32_t *t,
+                         const uint32_t *r, uint64_t n, uint32_t *out, hipStream_t s);
+// ratio vectors v_r for primes pr[0..n): v written at vpool + voff[i]
+hipError_t launch_ratio_vectors(const uint32_t *pr, const uint32_t *voff, uint32_t n,
+                                const uint64_t *work_prefix, uint64_t total_work,
+                                uint8_t *vpool, hipStream_t s);
+hipError_t launch_inverse_tables(const uint32_t *pr, const uint32_t *ioff, uint32_t n,
+                                 const uint64_t *prefix, uint64_t total, uint16_t *ipool,
+                                 hipStream_t s);
+hipError_t launch_vector_popcount(const uint32_t *pr, const uint32_t *voff, uint32_t n,
+                                  const uint8_t *vpool, uint32_t *out, hipStream_t s);
+hipError_t launch_pack_table(uint32_t r, const uint8_t *v, const uint16_t *inv, uint8_t *out,
+                             hipStream_t s);
+hipError_t launch_dense_windows(const uint32_t *pr, const uint32_t *voff, const uint32_t *ioff,
+                                const uint32_t *woff, uint32_t n, const uint64_t *prefix,
+                                uint64_t total, const uint8_t *vpool, const uint16_t *ipool,
+                                uint64_t *out, hipStream_t s);
+hipError_t launch_wheel(uint64_t *out, hipStream_t s);
+hipError_t launch_row_info(const uint32_t *primes16, const uint32_t *magic16, uint32_t n16,
+                           uint32_t pstart, uint64_t count, RowInfo *out, hipStream_t s);
+hipError_t launch_sweep(const SweepParams &P, int grid, size_t lds_bytes, hipStream_t s);
+hipError_t sweep_max_lds(size_t *bytes);
+// sorts n <= cap entries (n read from device) ascending by (req, idx) into out
+hipError_t launch_sort_surv(SurvEntry *a, SurvEntry *tmp, const unsigned long long *n_dev,
+                            uint64_t cap, SurvEntry **out, hipStream_t s);
+
+// ---- root check (kernels_roots.hip) ----
+struct RootCand {
+    uint32_t p, q;
+    uint32_t nf;           // distinct primes of the constant's square root
+    uint32_t pad;
+    uint32_t fp[20];       // those primes
+    uint32_t fe[20];       // exponents (in p^5 q^5, or p^4 / q^4 on an axis)
+    uint64_t bound;        // every positive root t is <= bound
+    uint64_t ndiv;         // number of divisors (saturating)
+};
+struct RootHit {
+    uint32_t cand;         // index of the pair
+    uint32_t pad;
+    uint64_t t;
+};
+hipError_t launch_root_factor(const uint32_t *p, const uint32_t *q, uint64_t n,
+                              const uint32_t *primes16, const uint32_t *magic16, uint32_t n16,
+                              RootCand *out, hipStream_t s);
+hipError_t launch_root_eval(const RootCand *c, uint64_t n_cand, const uint64_t *prefix,
+                            uint64_t w0, uint64_t nwork, RootHit *hits, uint64_t cap,
+                            unsigned long long *n_hits, hipStream_t s);
+
+}  // namespace cuboid

@@ -1,0 +1,401 @@
+// The sieve sweep of arXiv:1601.00636, section 2, on CDNA4.
+//
+// Each wavefront owns 64 consecutive rows p (one per lane) and walks the
+// columns q in windows of 64, so one 64-bit mask per lane holds the state of
+// 64 pairs.  Per window:
+//   1. coprimality (Conjecture 1.1 domain): a wheel lookup clears the q sharing
+//      a factor 2, 3, 5 or 7 with p, and each larger prime factor of p clears
+//      its multiples by a shifted bit pattern;
+//   2. dense primes: for the first K non-trivial primes r (ascending) one LDS
+//      read fetches u_r(p mod r, q mod r) for all 64 columns at once, the
+//      pairs it rejects are counted for r and dropped;
+//   3. the rare windows with pairs left are queued per wave; when 64 are
+//      queued every lane takes one and tests its pairs against the remaining
+//      primes in ascending order through the ratio-form tables, so the first
+//      rejecting prime is counted and unrejected pairs are appended as
+//      survivors.
+// The flattened space of 64x64 units over all requests of a launch is split
+// evenly over the persistent grid.
+#include "devmath.h"
+#include "internal.h"
+
+namespace cuboid {
+
+namespace {
+
+struct QEntry {
+    uint32_t p;
+    uint32_t qb;
+    uint64_t mask;
+};
+static_assert(sizeof(QEntry) == kQueueEntryBytes, "queue entry size");
+
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+    return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        uint32_t w = __shfl_xor(v, o, kWave);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// x mod d for a per-lane divisor d >= 1 (used at segment setup only)
+__device__ __forceinline__ uint32_t mod_var(uint32_t x, uint32_t d) { return x % d; }
+
+// Tests the pairs of one queued window against the deep primes, in ascending
+// order; counts the first rejecting prime, appends unrejected pairs.
+__device__ __forceinline__ void deep_window(const SweepParams &P, const QEntry e, uint32_t ri,
+                                            const ReqDesc &R, uint32_t *dcnt) {
+    uint64_t mask = e.mask;
+    const uint64_t width = (uint64_t)R.q1 - R.q0 + 1;
+    while (mask) {
+        const uint32_t j = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        const uint32_t q = e.qb + j;
+        bool rejected = false;
+        for (uint32_t i = 0; i < P.n_deep; ++i) {
+            const DeepPrime d = P.deep[i];
+            const uint32_t a = modr(e.p, d.r, d.m), b = modr(q, d.r, d.m);
+            if (a == 0 || b == 0) continue;
+            const uint32_t x = mulr(a, P.ipool[d.ioff + b], d.r, d.m);
+            if (P.vpool[d.voff + x]) {
+                if (i < kDeepCounters)
+                    atomicAdd(&dcnt[i], 1u);
+                else
+                    atomicAdd(&P.counts[(uint64_t)ri * P.nc + P.K + i], 1ull);
+                rejected = true;
+                break;
+            }
+        }
+        if (!rejected) {
+            const unsigned long long pos = atomicAdd(P.surv_n, 1ull);
+            if (pos < P.surv_cap) {
+                SurvEntry s;
+                s.idx = (uint64_t)(e.p - R.ip0) * width + (q - R.q0);
+                s.req = ri + P.req_base;
+                s.pad = 0;
+                P.surv[pos] = s;
+            }
+        }
+    }
+}
+
+template <int KD>
+__global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepParams P) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid >> 6;
+    uint64_t *sdense = (uint64_t *)smem;
+    uint64_t *swheel = sdense + P.dense_words;
+    unsigned char *wave_area = (unsigned char *)(swheel + kWheelSubsets * kWheel) +
+                               (size_t)wv * kPerWaveBytes;
+    QEntry *queue = (QEntry *)wave_area;
+    uint32_t *dcnt = (uint32_t *)(wave_area + kQueueCap * sizeof(QEntry));
+
+    for (uint32_t i = tid; i < P.dense_words; i += blockDim.x) sdense[i] = P.dense_tab[i];
+    for (uint32_t i = tid; i < kWheelSubsets * kWheel; i += blockDim.x) swheel[i] = P.wheel[i];
+    for (uint32_t i = lane; i < kDeepCounters; i += kWave) dcnt[i] = 0;
+    __syncthreads();
+
+    const uint32_t wheel_byte = P.dense_words * 8;
+    const uint64_t nwaves = (uint64_t)gridDim.x * kWavesPerWG;
+    const uint64_t w = (uint64_t)blockIdx.x * kWavesPerWG + wv;
+    const uint64_t qd = P.n_units / nwaves, rd = P.n_units % nwaves;
+    uint64_t u = uni64(qd * w + (rd * w) / nwaves);
+    const uint64_t uend = uni64(qd * (w + 1) + (rd * (w + 1)) / nwaves);
+    if (u >= uend) return;
+
+    // request holding unit u: last i with req[i].unit0 <= u
+    uint32_t ri;
+    {
+        uint32_t lo = 0, hi = P.n_req;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (uni64(P.req[mid].unit0) <= u) lo = mid; else hi = mid;
+        }
+        ri = uni(lo);
+    }
+
+    uint32_t cnt[KD + 1];
+    for (int k = 0; k <= KD; ++k) cnt[k] = 0;
+    uint32_t npairs = 0;
+    uint32_t qn = 0;            // queued windows (wave-uniform)
+    uint32_t since_flush = 0;   // windows since counters were flushed
+
+    auto drain = [&](uint32_t n, const ReqDesc &R) {
+        __builtin_amdgcn_wave_barrier();
+        if (lane < n) deep_window(P, queue[qn - n + lane], ri, R, dcnt);
+        __builtin_amdgcn_wave_barrier();
+        qn -= n;
+    };
+
+    auto flush = [&](const ReqDesc &R) {
+        while (qn) drain(qn < kWave ? qn : kWave, R);
+        const uint64_t cbase = (uint64_t)ri * P.nc;
+#pragma unroll
+        for (int k = 0; k < KD; ++k) {
+            const uint32_t s = wave_sum(cnt[k]);
+            if (lane == 0 && s) atomicAdd(&P.counts[cbase + k], (unsigned long long)s);
+            cnt[k] = 0;
+        }
+        const uint32_t s = wave_sum(npairs);
+        if (lane == 0 && s) atomicAdd(&P.pairs[ri], (unsigned long long)s);
+        npairs = 0;
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t ndc = P.n_deep < kDeepCounters ? P.n_deep : kDeepCounters;
+        for (uint32_t i = lane; i < ndc; i += kWave) {
+            const uint32_t v = dcnt[i];
+            if (v) {
+                atomicAdd(&P.counts[cbase + KD + i], (unsigned long long)v);
+                dcnt[i] = 0;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        since_flush = 0;
+    };
+
+    while (u < uend) {
+        ReqDesc R = P.req[ri];
+        R.p0 = uni(R.p0); R.p1 = uni(R.p1); R.q0 = uni(R.q0); R.q1 = uni(R.q1);
+        R.nrb = uni(R.nrb); R.nwin = uni(R.nwin); R.unit0 = uni64(R.unit0);
+        R.rows_p0 = uni(R.rows_p0); R.ip0 = uni(R.ip0);
+        const uint64_t rend = R.unit0 + (uint64_t)R.nrb * R.nwin;
+        if (u >= rend) {
+            flush(R);
+            ri = uni(ri + 1);
+            continue;
+        }
+        const uint64_t local = u - R.unit0;
+        const uint32_t rb = uni((uint32_t)(local / R.nwin));
+        const uint32_t win0 = uni((uint32_t)(local % R.nwin));
+        uint64_t seg_end = R.unit0 + (uint64_t)(rb + 1) * R.nwin;
+        if (seg_end > uend) seg_end = uend;
+        const uint32_t nw = uni((uint32_t)(seg_end - u));
+
+        // ---- segment setup: 64 rows, starting column qs ----
+        const uint64_t p64 = (uint64_t)R.p0 + (uint64_t)rb * kWave + lane;
+        const bool valid = p64 <= R.p1;
+        const uint32_t p = valid ? (uint32_t)p64 : 1u;
+        RowInfo rinfo;
+        if (valid) {
+            rinfo = R.rows[p - R.rows_p0];
+        } else {
+            rinfo.meta = 0;
+            for (int f = 0; f < kMaxBigFactors; ++f) rinfo.f[f] = 0;
+        }
+        const uint64_t rowmask = valid ? ~0ull : 0ull;
+        const uint32_t nf = (rinfo.meta >> 4) & 15;
+        const uint32_t nfmax = uni(wave_max(nf));
+        const uint32_t wheel_lane = wheel_byte + (rinfo.meta & 15) * (kWheel * 8);
+        const uint32_t qs = R.q0 + win0 * kWave;
+
+        uint32_t lb[KD + 1], ok[KD + 1];
+#pragma unroll
+        for (int k = 0; k < KD; ++k) {
+            lb[k] = P.doff[k] + modr(p, P.dr[k], P.dm[k]) * P.dr[k] * 8;
+            ok[k] = uni(modr(qs, P.dr[k], P.dm[k]));
+        }
+        uint32_t o210 = uni(qs % kWheel);
+
+        uint32_t fo[kMaxBigFactors], fd[kMaxBigFactors], fl[kMaxBigFactors];
+        uint64_t fp[kMaxBigFactors];
+#pragma unroll
+        for (int f = 0; f < kMaxBigFactors; ++f) {
+            if ((uint32_t)f < nf) {
+                const uint32_t l = rinfo.f[f];
+                const uint32_t rem = mod_var(qs, l);
+                fl[f] = l;
+                fo[f] = rem ? l - rem : 0;             // distance to the next multiple
+                fd[f] = l > kWave ? (uint32_t)kWave : (uint32_t)kWave % l;
+                uint64_t pat = 0;
+                for (uint32_t j = 0; j < (uint32_t)kWave; j += l) pat |= 1ull << j;
+                fp[f] = pat;
+            } else {
+                fl[f] = 0; fd[f] = 0; fo[f] = 0xffffffffu; fp[f] = 0;
+            }
+        }
+
+        // ---- windows ----
+        for (uint32_t k = 0; k < nw; ++k) {
+            const uint32_t qb = qs + k * kWave;
+            const uint32_t rem = R.q1 - qb + 1;
+            uint64_t alive = (rem >= (uint32_t)kWave ? ~0ull : ((1ull << rem) - 1)) & rowmask;
+            uint64_t nc = *(const uint64_t *)(smem + wheel_lane + o210 * 8);
+#pragma unroll
+            for (int f = 0; f < kMaxBigFactors; ++f) {
+                if ((uint32_t)f < nfmax) {
+                    nc |= fo[f] < (uint32_t)kWave ? (fp[f] << fo[f]) : 0ull;
+                    const uint32_t t = fo[f] - fd[f];
+                    const uint32_t t2 = t + fl[f];
+                    fo[f] = t < t2 ? t : t2;
+                }
+            }
+            alive &= ~nc;
+            if (qb == 1) {
+                if (p == 1) alive &= ~1ull;   // (1, 1) is coprime but p = q
+            }
+            npairs += __popcll(alive);
+#pragma unroll
+            for (int d = 0; d < KD; ++d) {
+                const uint64_t win = *(const uint64_t *)(smem + lb[d] + ok[d] * 8);
+                const uint64_t hit = alive & win;
+                cnt[d] += __popcll(hit);
+                alive ^= hit;
+                ok[d] += P.dstep[d];
+                if (ok[d] >= P.dr[d]) ok[d] -= P.dr[d];
+            }
+            o210 += kWave;
+            if (o210 >= (uint32_t)kWheel) o210 -= kWheel;
+
+            const uint64_t bal = __ballot(alive != 0);
+            if (bal) {
+                const uint32_t pos = qn + lane_rank(bal);
+                if (alive) {
+                    QEntry e;
+                    e.p = p; e.qb = qb; e.mask = alive;
+                    queue[pos] = e;
+                }
+                qn = uni(qn + (uint32_t)__popcll(bal));
+                if (qn >= (uint32_t)kWave) drain(kWave, R);
+            }
+            if (++since_flush >= (1u << 19)) flush(R);
+        }
+        u = seg_end;
+        if (u >= uend) flush(R);
+    }
+}
+
+
+// ---- survivor sort: block bitonic sort of 1024, then rank-based merges ----
+
+__device__ __forceinline__ bool surv_less(const SurvEntry &a, const SurvEntry &b) {
+    return a.req < b.req || (a.req == b.req && a.idx < b.idx);
+}
+
+constexpr int kSortTile = 1024;
+
+__global__ void __launch_bounds__(256) block_sort_kernel(SurvEntry *a, const unsigned long long *n_dev,
+                                                         uint64_t cap) {
+    __shared__ SurvEntry s[kSortTile];
+    const uint64_t n = *n_dev < cap ? *n_dev : cap;
+    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+    if (base >= n) return;
+    for (uint32_t i = threadIdx.x; i < kSortTile; i += blockDim.x) {
+        const uint64_t g = base + i;
+        if (g < n) {
+            s[i] = a[g];
+        } else {
+            s[i].idx = ~0ull; s[i].req = 0xffffffffu; s[i].pad = 0;
+        }
+    }
+    __syncthreads();
+    for (uint32_t k = 2; k <= (uint32_t)kSortTile; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < (uint32_t)kSortTile; i += blockDim.x) {
+                const uint32_t ixj = i ^ j;
+                if (ixj > i) {
+                    const bool up = (i & k) == 0;
+                    const SurvEntry x = s[i], y = s[ixj];
+                    if (up ? surv_less(y, x) : surv_less(x, y)) { s[i] = y; s[ixj] = x; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t i = threadIdx.x; i < kSortTile; i += blockDim.x) {
+        const uint64_t g = base + i;
+        if (g < n) a[g] = s[i];
+    }
+}
+
+// Merge sorted runs of length L pairwise.  Keys are distinct, so an element's
+// place is its rank in its own run plus the number of smaller keys in the
+// partner run.  A pass with L >= n only copies.
+__global__ void merge_pass_kernel(const SurvEntry *src, SurvEntry *dst,
+                                  const unsigned long long *n_dev, uint64_t cap, uint64_t L) {
+    const uint64_t n = *n_dev < cap ? *n_dev : cap;
+    for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < n;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const SurvEntry x = src[g];
+        if (L >= n) { dst[g] = x; continue; }
+        const uint64_t base = (g / (2 * L)) * (2 * L);
+        const uint64_t mid = base + L < n ? base + L : n;
+        const uint64_t end = base + 2 * L < n ? base + 2 * L : n;
+        uint64_t lo, hi;
+        if (g < mid) { lo = mid; hi = end; } else { lo = base; hi = mid; }
+        const uint64_t start = lo;
+        while (lo < hi) {   // first position whose key is not below x
+            const uint64_t m = (lo + hi) >> 1;
+            if (surv_less(src[m], x)) lo = m + 1; else hi = m;
+        }
+        const uint64_t below = lo - start;
+        dst[g < mid ? g + below : base + (g - mid) + below] = x;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_sweep(const SweepParams &P, int grid, size_t lds_bytes, hipStream_t s) {
+    if (P.K > (uint32_t)kKMax) return hipErrorInvalidValue;
+    if (P.n_units == 0) return hipSuccess;
+    const dim3 g(grid), b(kWave * kWavesPerWG);
+    switch (P.K) {
+#define CUBOID_SWEEP_CASE(k) \
+    case k: hipLaunchKernelGGL(sweep_kernel<k>, g, b, lds_bytes, s, P); break;
+        CUBOID_SWEEP_CASE(0) CUBOID_SWEEP_CASE(1) CUBOID_SWEEP_CASE(2) CUBOID_SWEEP_CASE(3)
+        CUBOID_SWEEP_CASE(4) CUBOID_SWEEP_CASE(5) CUBOID_SWEEP_CASE(6) CUBOID_SWEEP_CASE(7)
+        CUBOID_SWEEP_CASE(8) CUBOID_SWEEP_CASE(9) CUBOID_SWEEP_CASE(10) CUBOID_SWEEP_CASE(11)
+        CUBOID_SWEEP_CASE(12)
+#undef CUBOID_SWEEP_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t sweep_max_lds(size_t *bytes) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    int v = 0;
+    e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return e;
+    *bytes = (size_t)v;
+    return hipSuccess;
+}
+
+hipError_t launch_sort_surv(SurvEntry *a, SurvEntry *tmp, const unsigned long long *n_dev,
+                            uint64_t cap, SurvEntry **out, hipStream_t s) {
+    *out = a;
+    if (cap == 0) return hipSuccess;
+    const uint64_t tiles = (cap + kSortTile - 1) / kSortTile;
+    hipLaunchKernelGGL(block_sort_kernel, dim3((unsigned)tiles), dim3(256), 0, s, a, n_dev, cap);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    SurvEntry *src = a, *dst = tmp;
+    for (uint64_t L = kSortTile; L < cap; L *= 2) {
+        uint64_t g = (cap + 255) / 256;
+        if (g > (1u << 16)) g = 1u << 16;
+        hipLaunchKernelGGL(merge_pass_kernel, dim3((unsigned)g), dim3(256), 0, s, src, dst, n_dev,
+                           cap, L);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        SurvEntry *t = src; src = dst; dst = t;
+    }
+    *out = src;
+    return hipSuccess;
+}
+
+}  // namespace cuboid

@@ -1,0 +1,286 @@
+// Table construction on the GPU: Q_pq(t) mod r evaluation, the unsolvability
+// tables of Definition 1.1 / eq. (2.3) of arXiv:1601.00636 in ratio form, the
+// paper's packed layout (eq. 2.6), the 64-bit window tables the sweep stages in
+// LDS, the coprimality wheel and per-row prime factors.
+#include "devmath.h"
+#include "internal.h"
+
+namespace cuboid {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline unsigned grid_for(uint64_t n, unsigned block = kBlock) {
+    uint64_t g = (n + block - 1) / block;
+    if (g > 1u << 20) g = 1u << 20;   // grid-stride beyond this
+    return (unsigned)(g ? g : 1);
+}
+
+__global__ void fill_u64_kernel(uint64_t *p, uint64_t n, uint64_t v) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void fill_u8_kernel(uint8_t *p, uint64_t n, uint8_t v) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// out[i] = Q_{p q}(t) mod r for arbitrary 2 <= r < 2^16
+__global__ void q_eval_kernel(const uint32_t *p, const uint32_t *q, const uint32_t *t,
+                              const uint32_t *rr, uint64_t n, uint32_t *out) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t r = rr[i];
+        const uint32_t m = (uint32_t)(0x100000000ull / r);
+        const QCoef c = q_coeffs(modr(p[i], r, m), modr(q[i], r, m), r, m);
+        const uint32_t tr = modr(t[i], r, m);
+        out[i] = q_eval_s(c, mulr(tr, tr, r, m), r, m);
+    }
+}
+
+// Ratio vector of a prime r: v[x] = u_r(x, 1).  For a, b != 0 the weight-20
+// homogeneity Q_{la,lb}(l^2 t) = l^20 Q_ab(t) gives u_r(a, b) = v[a / b]; the
+// row and column of 0 are solvable (t = 0).  Q depends on x only through x^2
+// and is even in t, so x and t run over half the residues.
+// Work item g: prime i = segment of g, x = 1 + (g - prefix[i]).
+__global__ void ratio_vector_kernel(const uint32_t *pr, const uint32_t *voff, uint32_t n,
+                                    const uint64_t *prefix, uint64_t total, uint8_t *vpool) {
+    for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < total;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t i = find_segment(prefix, n, g);
+        const uint32_t r = pr[i];
+        const uint32_t m = (uint32_t)(0x100000000ull / r);
+        const uint32_t x = 1 + (uint32_t)(g - prefix[i]);
+        const QCoef c = q_coeffs(x, 1, r, m);
+        const uint32_t tmax = (r == 2) ? 1 : (r - 1) / 2;
+        bool solvable = false;
+        uint32_t s = 0;                        // t^2 mod r, advanced by 2t + 1
+        for (uint32_t t = 0; t <= tmax; ++t) {
+            if (q_eval_s(c, s, r, m) == 0) { solvable = true; break; }
+            s = modr(s + 2 * t + 1, r, m);
+        }
+        const uint8_t u = solvable ? 0 : 1;
+        vpool[voff[i] + x] = u;
+        vpool[voff[i] + (r - x) % r] = u;
+    }
+}
+
+// Modular inverses b^(r-2) mod r for b in [1, r); entry 0 stays 0.
+__global__ void inverse_kernel(const uint32_t *pr, const uint32_t *ioff, uint32_t n,
+                               const uint64_t *prefix, uint64_t total, uint16_t *ipool) {
+    for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < total;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t i = find_segment(prefix, n, g);
+        const uint32_t r = pr[i];
+        const uint32_t m = (uint32_t)(0x100000000ull / r);
+        const uint32_t b = 1 + (uint32_t)(g - prefix[i]);
+        uint32_t e = r - 2, base = b, acc = 1 % r;
+        while (e) {
+            if (e & 1) acc = mulr(acc, base, r, m);
+            base = mulr(base, base, r, m);
+            e >>= 1;
+        }
+        ipool[ioff[i] + b] = (uint16_t)acc;
+    }
+}
+
+// Number of unsolvable ratio classes per prime (0 => table identically zero).
+__global__ void vector_popcount_kernel(const uint32_t *pr, const uint32_t *voff,
+                                       const uint8_t *vpool, uint32_t *out) {
+    __shared__ uint32_t part[kBlock];
+    const uint32_t i = blockIdx.x, r = pr[i];
+    uint32_t c = 0;
+    for (uint32_t x = threadIdx.x; x < r; x += blockDim.x) c += vpool[voff[i] + x];
+    part[threadIdx.x] = c;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[i] = part[0];
+}
+
+__device__ __forceinline__ uint32_t unsolv_bit(uint32_t a, uint32_t b, uint32_t r, uint32_t m,
+                                               const uint8_t *v, const uint16_t *inv) {
+    if (a == 0 || b == 0) return 0;
+    return v[mulr(a, inv[b], r, m)];
+}
+
+// eq. (2.6) layout: bit a*r + b of the byte string, least significant first
+__global__ void pack_table_kernel(uint32_t r, const uint8_t *v, const uint16_t *inv,
+                                  uint8_t *out) {
+    const uint32_t m = (uint32_t)(0x100000000ull / r);
+    const uint64_t nbits = (uint64_t)r * r, nbytes = (nbits + 7) / 8;
+    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < nbytes;
+         k += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t byte = 0;
+        for (uint32_t j = 0; j < 8; ++j) {
+            const uint64_t idx = 8 * k + j;
+            if (idx >= nbits) break;
+            uint32_t b;
+            const uint32_t a = divr((uint32_t)idx, r, m, &b);
+            byte |= unsolv_bit(a, b, r, m, v, inv) << j;
+        }
+        out[k] = (uint8_t)byte;
+    }
+}
+
+// Window table of a dense prime r: entry a*r + o holds the 64 bits
+// u_r(a, (o + j) mod r), j = 0..63, so that one 64-bit read answers a whole
+// run of 64 consecutive columns q with q mod r = o for row residue a.
+__global__ void dense_windows_kernel(const uint32_t *pr, const uint32_t *voff,
+                                     const uint32_t *ioff, const uint32_t *woff, uint32_t n,
+                                     const uint64_t *prefix, uint64_t total, const uint8_t *vpool,
+                                     const uint16_t *ipool, uint64_t *out) {
+    for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < total;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t i = find_segment(prefix, n, g);
+        const uint32_t r = pr[i];
+        const uint32_t m = (uint32_t)(0x100000000ull / r);
+        const uint32_t e = (uint32_t)(g - prefix[i]);
+        uint32_t o;
+        const uint32_t a = divr(e, r, m, &o);
+        const uint8_t *v = vpool + voff[i];
+        const uint16_t *inv = ipool + ioff[i];
+        uint64_t w = 0;
+        uint32_t b = o;
+        for (uint32_t j = 0; j < 64; ++j) {
+            w |= (uint64_t)unsolv_bit(a, b, r, m, v, inv) << j;
+            b = (b + 1 == r) ? 0 : b + 1;
+        }
+        out[woff[i] + e] = w;
+    }
+}
+
+// Coprimality wheel: entry s*210 + o has bit j set when o + j is divisible by
+// one of the primes of subset s of {2, 3, 5, 7} (bit 0 = 2, ..., bit 3 = 7).
+__global__ void wheel_kernel(uint64_t *out) {
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= kWheelSubsets * kWheel) return;
+    const uint32_t s = e / kWheel, o = e % kWheel;
+    const uint32_t sp[4] = {2, 3, 5, 7};
+    uint64_t w = 0;
+    for (uint32_t j = 0; j < 64; ++j) {
+        bool hit = false;
+        for (int k = 0; k < 4; ++k)
+            if (((s >> k) & 1) && (o + j) % sp[k] == 0) hit = true;
+        if (hit) w |= 1ull << j;
+    }
+    out[e] = w;
+}
+
+// Distinct prime factors of p = pstart + g by trial division with the primes
+// below 2^16 (enough for any uint32).  primes16 starts 2, 3, 5, 7, 11, ...
+__global__ void row_info_kernel(const uint32_t *primes16, const uint32_t *magic16, uint32_t n16,
+                                uint32_t pstart, uint64_t count, RowInfo *out) {
+    for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < count;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t x = pstart + (uint32_t)g;
+        RowInfo ri;
+        ri.meta = 0;
+        uint32_t nf = 0;
+        for (int k = 0; k < kMaxBigFactors; ++k) ri.f[k] = 0;
+        for (uint32_t i = 0; i < n16; ++i) {
+            const uint32_t l = primes16[i];
+            if ((uint64_t)l * l > x) break;
+            const uint32_t m = magic16[i];
+            uint32_t rem;
+            uint32_t qt = divr(x, l, m, &rem);
+            if (rem) continue;
+            if (i < 4) ri.meta |= 1u << i; else ri.f[nf++] = l;
+            do { x = qt; qt = divr(x, l, m, &rem); } while (rem == 0);
+        }
+        if (x > 1) {
+            // remaining cofactor is prime
+            if (x == 2) ri.meta |= 1; else if (x == 3) ri.meta |= 2;
+            else if (x == 5) ri.meta |= 4; else if (x == 7) ri.meta |= 8;
+            else ri.f[nf++] = x;
+        }
+        ri.meta |= nf << 4;
+        out[g] = ri;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s) {
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t *p, uint64_t n, uint8_t v, hipStream_t s) {
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(fill_u8_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_q_eval(const uint32_t *p, const uint32_t *q, const uint32_t *t,
+                         const uint32_t *r, uint64_t n, uint32_t *out, hipStream_t s) {
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(q_eval_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, p, q, t, r, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_ratio_vectors(const uint32_t *pr, const uint32_t *voff, uint32_t n,
+                                const uint64_t *prefix, uint64_t total, uint8_t *vpool,
+                                hipStream_t s) {
+    if (!total) return hipSuccess;
+    hipLaunchKernelGGL(ratio_vector_kernel, dim3(grid_for(total)), dim3(kBlock), 0, s, pr, voff,
+                       n, prefix, total, vpool);
+    return hipGetLastError();
+}
+
+hipError_t launch_inverse_tables(const uint32_t *pr, const uint32_t *ioff, uint32_t n,
+                                 const uint64_t *prefix, uint64_t total, uint16_t *ipool,
+                                 hipStream_t s) {
+    if (!total) return hipSuccess;
+    hipLaunchKernelGGL(inverse_kernel, dim3(grid_for(total)), dim3(kBlock), 0, s, pr, ioff, n,
+                       prefix, total, ipool);
+    return hipGetLastError();
+}
+
+hipError_t launch_vector_popcount(const uint32_t *pr, const uint32_t *voff, uint32_t n,
+                                  const uint8_t *vpool, uint32_t *out, hipStream_t s) {
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(vector_popcount_kernel, dim3(n), dim3(kBlock), 0, s, pr, voff, vpool, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_table(uint32_t r, const uint8_t *v, const uint16_t *inv, uint8_t *out,
+                             hipStream_t s) {
+    const uint64_t nbytes = ((uint64_t)r * r + 7) / 8;
+    hipLaunchKernelGGL(pack_table_kernel, dim3(grid_for(nbytes)), dim3(kBlock), 0, s, r, v, inv,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_windows(const uint32_t *pr, const uint32_t *voff, const uint32_t *ioff,
+                                const uint32_t *woff, uint32_t n, const uint64_t *prefix,
+                                uint64_t total, const uint8_t *vpool, const uint16_t *ipool,
+                                uint64_t *out, hipStream_t s) {
+    if (!total) return hipSuccess;
+    hipLaunchKernelGGL(dense_windows_kernel, dim3(grid_for(total)), dim3(kBlock), 0, s, pr, voff,
+                       ioff, woff, n, prefix, total, vpool, ipool, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_wheel(uint64_t *out, hipStream_t s) {
+    const uint32_t n = kWheelSubsets * kWheel;
+    hipLaunchKernelGGL(wheel_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_info(const uint32_t *primes16, const uint32_t *magic16, uint32_t n16,
+                           uint32_t pstart, uint64_t count, RowInfo *out, hipStream_t s) {
+    if (!count) return hipSuccess;
+    hipLaunchKernelGGL(row_info_kernel, dim3(grid_for(count)), dim3(kBlock), 0, s, primes16,
+                       magic16, n16, pstart, count, out);
+    return hipGetLastError();
+}
+
+}  // namespace cuboid

@@ -1,0 +1,121 @@
+// Host-side state of libcuboid (context, plans, device buffers).
+#pragma once
+
+#include <stdint.h>
+
+#include <atomic>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "cuboid.h"
+#include "internal.h"
+
+namespace cuboid {
+
+constexpr uint32_t kMaxPrimes = 6542;                 // primes below 2^16
+constexpr uint32_t kResidentRowsMax = 1u << 24;       // rows with resident factor lists
+constexpr uint64_t kBandRows = 1u << 22;              // rows per band beyond that
+constexpr uint64_t kMaxSurvScratch = 1ull << 26;      // survivors held on the device per call
+constexpr uint32_t kDefaultLdsBudget = 32 * 1024;     // LDS bytes for dense window tables
+
+// Grow-only device allocation.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t n);
+    void release();
+    ~DevBuf() { release(); }
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+};
+
+// Pinned host staging, grow-only.
+struct HostBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t n);
+    void release();
+    ~HostBuf() { release(); }
+    HostBuf() = default;
+    HostBuf(const HostBuf &) = delete;
+    HostBuf &operator=(const HostBuf &) = delete;
+};
+
+// Dense window tables for the first K non-trivial primes of a plan, and the
+// list of the remaining ("deep") primes.
+struct DenseSet {
+    uint32_t K = 0;
+    uint32_t dr[kKMax] = {0}, dm[kKMax] = {0}, dstep[kKMax] = {0}, doff[kKMax] = {0};
+    uint32_t words = 0;
+    DevBuf tab;
+    uint32_t n_deep = 0;
+    DevBuf deep;
+};
+
+// Everything the GPU needs for one canonical (sorted) prime list.
+struct Plan {
+    std::vector<uint32_t> primes;                 // ascending
+    std::vector<uint8_t> trivial;                 // table identically zero
+    std::vector<uint32_t> unsolvable_classes;     // per prime, from the ratio vector
+    std::vector<uint32_t> nontriv_idx;            // indices of non-trivial primes, ascending
+    std::vector<uint32_t> voff, ioff;             // per prime offsets into the pools
+    DevBuf vpool;                                 // ratio vectors, one byte per class
+    DevBuf ipool;                                 // inverse tables, uint16
+    std::map<uint32_t, std::unique_ptr<DenseSet>> dense;
+};
+
+}  // namespace cuboid
+
+struct cuboid_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::recursive_mutex mu;
+    std::atomic<int> servers{0};
+    int cu_count = 0;
+    size_t max_lds = 0;
+    char arch[64] = {0};
+
+    // constant tables
+    cuboid::DevBuf primes16, magic16;   // primes below 2^16 and floor(2^32 / p)
+    uint32_t n16 = 0;
+    cuboid::DevBuf wheel;               // 16 x 210 coprimality windows
+
+    // resident factor lists of rows 1..rows_R
+    cuboid::DevBuf rows;
+    uint32_t rows_R = 0;
+    cuboid::DevBuf band_rows;
+
+    std::map<std::vector<uint32_t>, std::unique_ptr<cuboid::Plan>> plans;
+    std::map<std::vector<uint32_t>, cuboid_tuning> tunings;
+
+    // per-call scratch
+    cuboid::DevBuf reqbuf, counts, pairs, surv, surv_tmp, surv_n;
+    cuboid::HostBuf req_stage;
+
+    // timing
+    bool timing = false;
+    hipEvent_t ev_sweep0 = nullptr, ev_sweep1 = nullptr, ev_total0 = nullptr, ev_total1 = nullptr;
+    cuboid_timing last = {0, 0, 0, 0, 0};
+};
+
+namespace cuboid {
+
+const char *status_text(int s);
+bool is_prime_u32(uint32_t x);
+int canonical_primes(const uint32_t *primes, uint32_t n, std::vector<uint32_t> *sorted);
+int build_plan(cuboid_ctx *ctx, const std::vector<uint32_t> &primes, Plan **out);
+uint32_t default_dense(const Plan &pl, uint32_t lds_budget);
+int build_dense(cuboid_ctx *ctx, Plan *pl, uint32_t K, DenseSet **out);
+int ensure_rows(cuboid_ctx *ctx, uint32_t p_max);
+cuboid_tuning tuning_for(cuboid_ctx *ctx, const std::vector<uint32_t> &primes, const Plan &pl);
+int rect_valid(uint32_t p0, uint32_t p1, uint32_t q0, uint32_t q1);
+int sieve_rects(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes,
+                const std::vector<cuboid_request> &rects, uint64_t surv_cap_total,
+                hipStream_t s, std::vector<std::vector<uint64_t>> *counts_out,
+                std::vector<uint64_t> *pairs_out, std::vector<SurvEntry> *surv_out,
+                uint64_t *n_surv_out);
+
+}  // namespace cuboid
