@@ -27,6 +27,14 @@ bool ctx_live(cuboid_ctx *ctx) {
     return std::find(g_ctxs.begin(), g_ctxs.end(), ctx) != g_ctxs.end();
 }
 
+}  // namespace
+
+namespace cuboid {
+bool ctx_is_live(cuboid_ctx *ctx) { return ctx_live(ctx); }
+}  // namespace cuboid
+
+namespace {
+
 int set_device(cuboid_ctx *ctx) {
     return hipSetDevice(ctx->device) == hipSuccess ? CUBOID_OK : CUBOID_E_DEVICE;
 }

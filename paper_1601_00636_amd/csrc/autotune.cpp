@@ -72,7 +72,7 @@ void append_cache(const char *path, const std::string &arch, const std::string &
 
 extern "C" int cuboid_autotune(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes,
                                const char *cache_path, cuboid_tuning *out) {
-    if (!ctx) return CUBOID_E_NOT_LOADED;
+    if (!ctx_is_live(ctx)) return CUBOID_E_NOT_LOADED;
     std::vector<uint32_t> sorted;
     int st = canonical_primes(primes, n_primes, &sorted);
     if (st) return st;

@@ -104,6 +104,7 @@ struct cuboid_ctx {
 namespace cuboid {
 
 const char *status_text(int s);
+bool ctx_is_live(cuboid_ctx *ctx);
 bool is_prime_u32(uint32_t x);
 int canonical_primes(const uint32_t *primes, uint32_t n, std::vector<uint32_t> *sorted);
 int build_plan(cuboid_ctx *ctx, const std::vector<uint32_t> &primes, Plan **out);

@@ -1,0 +1,99 @@
+"""The C-ABI library on the CPU: it loads, exports every entry point the
+header declares, and its host-only functions behave (no GPU calls here)."""
+import random
+import re
+
+import pytest
+
+from oracle import poly
+from paper_1601_00636_amd import binding as cb
+from tests.conftest import ROOT
+
+
+def _declared():
+    txt = open(ROOT + "/include/cuboid.h").read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(cuboid_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = cb.lib()
+    names = _declared()
+    assert "cuboid_sieve_range" in names and "cuboid_root_check" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert missing == []
+
+
+def test_status_strings_and_version():
+    assert cb.cuboid_version().endswith("gfx950")
+    for s in range(9):
+        assert cb.cuboid_status_string(s)
+    assert "unknown" in cb.cuboid_status_string(99)
+
+
+def test_canonical_primes():
+    s, triv = cb.cuboid_canonical_primes([31, 2, 11, 7, 5, 3, 13])
+    assert s.tolist() == [2, 3, 5, 7, 11, 13, 31]
+    assert triv.tolist() == [True, True, True, True, False, False, False]
+    for bad in ([], [4], [11, 11], [65537], [1], [65536]):
+        with pytest.raises(cb.CuboidError) as e:
+            cb.cuboid_canonical_primes(bad)
+        assert e.value.status == cb.E_PRIMES
+    s, _ = cb.cuboid_canonical_primes([65521, 2])
+    assert s.tolist() == [2, 65521]
+
+
+def test_exact_value_matches_python_ints():
+    rng = random.Random(17)
+    for _ in range(3000):
+        p, q = rng.randrange(0, 2**31), rng.randrange(0, 2**31)
+        t = rng.randrange(0, 2**64)
+        assert cb.cuboid_exact_value(p, q, t) == poly.q_value(p, q, t)
+    for p, q, t in [(0, 0, 0), (1, 2, 0), (2**31 - 1, 2**31 - 1, 2**64 - 1), (5, 0, 25)]:
+        assert cb.cuboid_exact_value(p, q, t) == poly.q_value(p, q, t)
+
+
+def test_exact_check_roots_and_flags():
+    for p in (1, 2, 12, 1000, 2**31 - 1):
+        z, f = cb.cuboid_exact_check(p, p, p * p)
+        assert z and f == poly.theorem_1_1_flags(p, p, p * p)
+        assert not cb.cuboid_exact_check(p, p, p * p + 1)[0]
+        z, _ = cb.cuboid_exact_check(p, 0, p * p)
+        assert z
+    rng = random.Random(3)
+    for _ in range(2000):
+        p, q, t = rng.randrange(0, 2**31), rng.randrange(0, 2**31), rng.randrange(0, 2**64)
+        assert cb.cuboid_exact_check(p, q, t)[1] == poly.theorem_1_1_flags(p, q, t)
+    with pytest.raises(cb.CuboidError) as e:
+        cb.cuboid_exact_check(2**31, 1, 5)
+    assert e.value.status == cb.E_LIMIT
+
+
+def test_create_without_gpu_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(cb.CuboidError) as e:
+        cb.cuboid_create(0)
+    assert e.value.status == cb.E_DEVICE
+
+
+def test_calls_on_null_context_are_refused():
+    import ctypes
+    h = ctypes.c_void_p(0)
+    assert cb.cuboid_destroy(h) == cb.E_NOT_LOADED
+    with pytest.raises(cb.CuboidError) as e:
+        cb.cuboid_sieve_range(h, 1, 5, 1, 5, [11])
+    assert e.value.status == cb.E_NOT_LOADED
+    bogus = ctypes.c_void_p(0x1234560)
+    with pytest.raises(cb.CuboidError) as e:
+        cb.cuboid_root_check(bogus, [1], [2])
+    assert e.value.status == cb.E_NOT_LOADED
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, ROOT + "/bench.py", "--gpus", "2"],
+                       stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+    assert r.returncode == 2 and "one GPU" in r.stderr
