@@ -108,18 +108,25 @@ def main():
     _, trivial = cb.cuboid_canonical_primes(primes)
     trivial = np.array([r in (2, 3, 5, 7) for r in primes])
 
+    req_arr = np.asarray(reqs, dtype=np.int64)
+
     def step():
-        st, out = cb.cuboid_sieve_batch(ctx, reqs, primes, caps=256, stream=stream)
+        st, out = cb.cuboid_sieve_batch(ctx, req_arr, primes, caps=256, stream=stream)
         if st != cb.OK:
             raise RuntimeError("batch status %d" % st)
         sweep = cb.cuboid_last_timing(ctx)
-        ps, qs = [], []
-        for (p0, p1, q0, q1), r in zip(reqs, out):
-            w = q1 - q0 + 1
-            for i in r["survivors"]:
-                ps.append(p0 + int(i) // w)
-                qs.append(q0 + int(i) % w)
-        roots = cb.cuboid_root_check(ctx, ps, qs) if ps else []
+        ns = out.n_survivors.astype(np.int64)
+        ps = qs = []
+        if ns.sum():
+            # survivor index i of request j is (p - p0_j) * width_j + (q - q0_j)
+            owner = np.repeat(np.arange(len(ns)), ns)
+            take = np.concatenate([np.arange(int(out.offsets[j]), int(out.offsets[j]) + int(ns[j]))
+                                   for j in np.nonzero(ns)[0]])
+            idx = out.survivors_flat[take].astype(np.int64)
+            width = req_arr[owner, 3] - req_arr[owner, 2] + 1
+            ps = req_arr[owner, 0] + idx // width
+            qs = req_arr[owner, 2] + idx % width
+        roots = cb.cuboid_root_check(ctx, ps, qs) if len(ps) else []
         return out, len(ps), roots, sweep
 
     for _ in range(args.warmup):
@@ -134,8 +141,8 @@ def main():
     elapsed = time.perf_counter() - t0
     sweep_avg = float(np.mean(sweeps))
 
-    n_pairs = sum(r["n_pairs"] for r in out)
-    counts = np.sum([r["counts"] for r in out], axis=0)
+    n_pairs = int(out.n_pairs.sum())
+    counts = out.counts.sum(axis=0)
     value = n_pairs * args.steps / elapsed
     lookups, k_nt = mean_depth(counts, nsurv, primes, trivial)
     dbar = lookups / n_pairs
@@ -161,6 +168,7 @@ def main():
                    "n_requests": 4096, "coprime_pairs_per_step": n_pairs,
                    "survivors_per_step": nsurv, "roots_found": len(roots),
                    "tuning": tun},
+        "extras": {},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT32_PEAK / 1e12,
                      "unit": "Tops/s (INT32)", "frac": achieved / INT32_PEAK, "traffic": None,
                      "kernel": "sweep_kernel", "sweep_ms": sweep_avg,
@@ -169,7 +177,7 @@ def main():
     }
 
     if not args.no_extras:
-        extras = {}
+        extras = res["extras"]
         # the same 4096 rectangles as separate plain launches
         t0 = time.perf_counter()
         tot = 0
@@ -190,11 +198,11 @@ def main():
             torch.cuda.synchronize()
             reps.append(time.perf_counter() - t0)
         t3 = cb.cuboid_last_timing(ctx)
-        extras["plain_square_1e5"] = {"value": r3["n_pairs"] / float(np.median(reps)),
+        extras["plain_square_1e5"] = {"tuning": cb.cuboid_get_tuning(ctx, p3),
+                                      "value": r3["n_pairs"] / float(np.median(reps)),
                                       "ms": float(np.median(reps)) * 1e3,
                                       "sweep_ms": t3["sweep_ms"], "n_pairs": r3["n_pairs"],
                                       "sweep_pairs_per_s": r3["n_pairs"] / (t3["sweep_ms"] * 1e-3)}
-        res["extras"] = extras
 
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = run_cpu_baseline(reqs, primes, args.cpu_stride)

@@ -224,34 +224,60 @@ def cuboid_canonical_primes(primes):
     return out[:len(pr)], triv[:len(pr)].astype(bool)
 
 
+_RESULT_DTYPE = np.dtype([("survivors", "<u8"), ("cap", "<u8"), ("n_survivors", "<u8"),
+                          ("counts", "<u8"), ("n_pairs", "<u8"), ("status", "<i4"),
+                          ("reserved", "<u4")])
+assert _RESULT_DTYPE.itemsize == ctypes.sizeof(cuboid_result)
+
+
+class BatchResult:
+    """Per-request results of cuboid_sieve_batch as arrays: status[n],
+    counts[n, n_primes], n_pairs[n], n_survivors[n]; survivors of request i
+    are survivors_flat[offsets[i] : offsets[i] + n_survivors[i]] when
+    status[i] == OK.  Indexing gives one request as a dict."""
+
+    def __init__(self, status, counts, n_pairs, n_survivors, flat, offsets):
+        self.status, self.counts, self.n_pairs = status, counts, n_pairs
+        self.n_survivors, self.survivors_flat, self.offsets = n_survivors, flat, offsets
+
+    def __len__(self):
+        return len(self.status)
+
+    def survivors(self, i):
+        if self.status[i] != OK:
+            return None
+        a = int(self.offsets[i])
+        return self.survivors_flat[a:a + int(self.n_survivors[i])]
+
+    def __getitem__(self, i):
+        return dict(status=int(self.status[i]), counts=self.counts[i], n_pairs=int(self.n_pairs[i]),
+                    n_survivors=int(self.n_survivors[i]), survivors=self.survivors(i))
+
+    def __iter__(self):
+        return (self[i] for i in range(len(self)))
+
+
 def cuboid_sieve_batch(ctx, requests, primes, caps=1024, stream=None):
-    """requests: list of (p0, p1, q0, q1).  Returns (status, [dict per request])."""
+    """requests: (n, 4) array-like of (p0, p1, q0, q1).  Returns (status, BatchResult)."""
     pr = _arr(primes, np.uint32)
-    n = len(requests)
-    if isinstance(caps, int):
-        caps = [caps] * n
-    req = (cuboid_request * max(1, n))()
-    res = (cuboid_result * max(1, n))()
-    keep = []
-    for i, (a, b, c, d) in enumerate(requests):
-        req[i].p0, req[i].p1, req[i].q0, req[i].q1 = int(a), int(b), int(c), int(d)
-        sv = np.zeros(max(1, caps[i]), dtype=np.uint64)
-        ct = np.zeros(max(1, len(pr)), dtype=np.uint64)
-        keep.append((sv, ct))
-        res[i].survivors = _p(sv, u64)
-        res[i].cap = int(caps[i])
-        res[i].counts = _p(ct, u64)
-    st = _load().cuboid_sieve_batch(ctx, req, n, _p(pr, u32), len(pr), res, _stream(stream))
+    reqa = np.ascontiguousarray(np.asarray(requests, dtype=np.uint32).reshape(-1, 4))
+    n = reqa.shape[0]
+    caps = np.full(n, caps, dtype=np.uint64) if np.isscalar(caps) else _arr(caps, np.uint64)
+    offsets = np.zeros(n + 1, dtype=np.uint64)
+    np.cumsum(caps, out=offsets[1:])
+    flat = np.zeros(max(1, int(offsets[-1])), dtype=np.uint64)
+    counts = np.zeros((n, max(1, len(pr))), dtype=np.uint64)
+    res = np.zeros(max(1, n), dtype=_RESULT_DTYPE)
+    res["survivors"][:n] = flat.ctypes.data + offsets[:-1] * 8
+    res["cap"][:n] = caps
+    res["counts"][:n] = counts.ctypes.data + np.arange(n, dtype=np.uint64) * (counts.shape[1] * 8)
+    st = _load().cuboid_sieve_batch(ctx, reqa.ctypes.data_as(P(cuboid_request)), n, _p(pr, u32),
+                                    len(pr), res.ctypes.data_as(P(cuboid_result)),
+                                    _stream(stream))
     if st not in (OK, E_CAPACITY, E_LIMIT):
         _check(st, "cuboid_sieve_batch")
-    out = []
-    for i in range(n):
-        sv, ct = keep[i]
-        ns = res[i].n_survivors
-        out.append(dict(status=res[i].status, counts=ct[:len(pr)].copy(), n_pairs=res[i].n_pairs,
-                        n_survivors=ns,
-                        survivors=sv[:ns].copy() if res[i].status == OK else None))
-    return st, out
+    return st, BatchResult(res["status"][:n].copy(), counts[:, :len(pr)], res["n_pairs"][:n].copy(),
+                           res["n_survivors"][:n].copy(), flat, offsets)
 
 
 def cuboid_enable_timing(ctx, on=True):

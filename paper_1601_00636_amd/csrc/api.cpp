@@ -194,18 +194,15 @@ int cuboid_sieve_range(cuboid_ctx *ctx, uint32_t p0, uint32_t p1, uint32_t q0, u
     const std::vector<uint32_t> caller(primes, primes + n_primes);
     std::vector<cuboid_request> rects(1);
     rects[0].p0 = p0; rects[0].p1 = p1; rects[0].q0 = q0; rects[0].q1 = q1;
-    std::vector<std::vector<uint64_t>> cnt;
-    std::vector<uint64_t> pairs;
-    std::vector<SurvEntry> surv;
-    uint64_t nsurv = 0;
+    SieveOut so;
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
-    st = sieve_rects(ctx, caller, rects, cap, s, &cnt, &pairs, &surv, &nsurv);
+    st = sieve_rects(ctx, caller, rects, cap, s, &so);
     if (st) return st;
-    memcpy(counts, cnt[0].data(), n_primes * 8);
-    *n_pairs = pairs[0];
-    *n_survivors = nsurv;
-    if (nsurv > cap) return CUBOID_E_CAPACITY;
-    for (uint64_t i = 0; i < nsurv; ++i) survivors[i] = surv[i].idx;
+    memcpy(counts, so.counts.data(), n_primes * 8);
+    *n_pairs = so.pairs[0];
+    *n_survivors = so.n_surv;
+    if (so.n_surv > cap) return CUBOID_E_CAPACITY;
+    for (uint64_t i = 0; i < so.n_surv; ++i) survivors[i] = so.surv[i].idx;
     return CUBOID_OK;
 }
 
@@ -230,39 +227,36 @@ int cuboid_sieve_batch(cuboid_ctx *ctx, const cuboid_request *req, uint32_t n_re
     if (set_device(ctx)) return CUBOID_E_DEVICE;
     const std::vector<uint32_t> caller(primes, primes + n_primes);
     const std::vector<cuboid_request> rects(req, req + n_req);
-    std::vector<std::vector<uint64_t>> cnt;
-    std::vector<uint64_t> pairs;
-    std::vector<SurvEntry> surv;
-    uint64_t nsurv = 0;
+    SieveOut so;
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
     // a request may hold more survivors than its own cap while the total fits;
     // the device list holds up to the sum of the caps
-    st = sieve_rects(ctx, caller, rects, cap_total, s, &cnt, &pairs, &surv, &nsurv);
+    st = sieve_rects(ctx, caller, rects, cap_total, s, &so);
     if (st && st != CUBOID_E_LIMIT) return st;
-    if (st == CUBOID_OK && nsurv > cap_total && nsurv <= kMaxSurvScratch) {
+    if (st == CUBOID_OK && so.n_surv > cap_total && so.n_surv <= kMaxSurvScratch) {
         // some request holds more survivors than its cap: run again with room
         // for all of them so every other request still gets its full list
-        st = sieve_rects(ctx, caller, rects, nsurv, s, &cnt, &pairs, &surv, &nsurv);
+        st = sieve_rects(ctx, caller, rects, so.n_surv, s, &so);
         if (st && st != CUBOID_E_LIMIT) return st;
     }
     for (uint32_t i = 0; i < n_req; ++i) {
-        memcpy(res[i].counts, cnt[i].data(), n_primes * 8);
-        res[i].n_pairs = pairs[i];
+        memcpy(res[i].counts, so.counts.data() + (size_t)i * n_primes, n_primes * 8);
+        res[i].n_pairs = so.pairs[i];
     }
-    std::vector<uint64_t> per(n_req, 0);
-    int any_cap = 0;
-    if (st == CUBOID_E_LIMIT || surv.size() != nsurv) {
+    if (st == CUBOID_E_LIMIT || so.surv.size() != so.n_surv) {
         // survivors beyond what the device list holds: numbers only, from the
         // conservation law sum(counts) + survivors = pairs
         for (uint32_t i = 0; i < n_req; ++i) {
             uint64_t sc = 0;
-            for (uint32_t k = 0; k < n_primes; ++k) sc += cnt[i][k];
-            res[i].n_survivors = pairs[i] - sc;
+            for (uint32_t k = 0; k < n_primes; ++k) sc += so.counts[(size_t)i * n_primes + k];
+            res[i].n_survivors = so.pairs[i] - sc;
             res[i].status = res[i].n_survivors > res[i].cap ? CUBOID_E_CAPACITY : CUBOID_E_LIMIT;
         }
         return CUBOID_E_LIMIT;
     }
-    for (const SurvEntry &e : surv) per[e.req]++;
+    std::vector<uint64_t> per(n_req, 0);
+    for (const SurvEntry &e : so.surv) per[e.req]++;
+    int any_cap = 0;
     size_t k = 0;
     for (uint32_t i = 0; i < n_req; ++i) {
         res[i].n_survivors = per[i];
@@ -273,7 +267,7 @@ int cuboid_sieve_batch(cuboid_ctx *ctx, const cuboid_request *req, uint32_t n_re
             continue;
         }
         res[i].status = CUBOID_OK;
-        for (uint64_t j = 0; j < per[i]; ++j) res[i].survivors[j] = surv[k++].idx;
+        for (uint64_t j = 0; j < per[i]; ++j) res[i].survivors[j] = so.surv[k++].idx;
     }
     return any_cap ? CUBOID_E_CAPACITY : CUBOID_OK;
 }

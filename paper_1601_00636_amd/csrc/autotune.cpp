@@ -91,16 +91,18 @@ extern "C" int cuboid_autotune(cuboid_ctx *ctx, const uint32_t *primes, uint32_t
     const uint32_t budget = (uint32_t)std::min<size_t>(ctx->max_lds - kSweepFixedLds, 96 * 1024);
     const uint32_t kmax = default_dense(*pl, budget);
     const uint32_t cus = (uint32_t)ctx->cu_count;
-    // sample: 8192 rows x 65536 columns near 2^19, the scale of the batched workloads
+    // sample: 32768 rows x 65536 columns near 2^19 (the scale of the batched
+    // workloads), about 2^19 units: enough work per wave for the timing to
+    // reflect a full launch
     std::vector<cuboid_request> rect(1);
-    rect[0].p0 = 1u << 19; rect[0].p1 = (1u << 19) + 8191;
+    rect[0].p0 = 1u << 19; rect[0].p1 = (1u << 19) + 32767;
     rect[0].q0 = 1u << 19; rect[0].q1 = (1u << 19) + 65535;
     const bool saved_timing = ctx->timing;
     ctx->timing = true;
     double best_ms = 1e30;
     best.dense_primes = 0; best.workgroups = 2 * cus; best.lds_budget = budget; best.reserved = 0;
     const uint32_t klo = kmax > 5 ? kmax - 5 : 0;
-    const uint32_t wgs[4] = {cus, 2 * cus, 4 * cus, 8 * cus};
+    const uint32_t wgs[4] = {cus, 2 * cus, 3 * cus, 4 * cus};
     for (uint32_t K = klo; K <= kmax; ++K) {
         for (uint32_t w : wgs) {
             cuboid_tuning t;
@@ -108,11 +110,8 @@ extern "C" int cuboid_autotune(cuboid_ctx *ctx, const uint32_t *primes, uint32_t
             ctx->tunings[sorted] = t;
             double ms_best = 1e30;
             for (int rep = 0; rep < 3; ++rep) {
-                std::vector<std::vector<uint64_t>> cnt;
-                std::vector<uint64_t> pairs;
-                std::vector<SurvEntry> surv;
-                uint64_t ns = 0;
-                st = sieve_rects(ctx, sorted, rect, 1 << 16, ctx->stream, &cnt, &pairs, &surv, &ns);
+                SieveOut so;
+                st = sieve_rects(ctx, sorted, rect, 1 << 16, ctx->stream, &so);
                 if (st) break;
                 ms_best = std::min(ms_best, ctx->last.sweep_ms);
             }

@@ -348,18 +348,18 @@ int fetch_survivors(cuboid_ctx *ctx, uint64_t n, std::vector<SurvEntry> *out, hi
     return CUBOID_OK;
 }
 
-// Map canonical non-trivial counts to the caller's prime order.
-void map_counts(const Plan &pl, const std::vector<uint32_t> &caller, const uint64_t *canon,
-                uint64_t *out) {
-    // rank of each non-trivial prime in canonical order
+// For each prime of the caller's list, its index among the plan's
+// non-trivial primes (canonical counter slot), or -1 for a trivial prime.
+std::vector<int32_t> count_columns(const Plan &pl, const std::vector<uint32_t> &caller) {
+    std::vector<int32_t> col(caller.size(), -1);
     for (size_t i = 0; i < caller.size(); ++i) {
-        const uint32_t r = caller[i];
-        const size_t pos = std::lower_bound(pl.primes.begin(), pl.primes.end(), r) - pl.primes.begin();
-        if (pl.trivial[pos]) { out[i] = 0; continue; }
-        const size_t k = std::lower_bound(pl.nontriv_idx.begin(), pl.nontriv_idx.end(), (uint32_t)pos) -
-                         pl.nontriv_idx.begin();
-        out[i] = canon[k];
+        const size_t pos =
+            std::lower_bound(pl.primes.begin(), pl.primes.end(), caller[i]) - pl.primes.begin();
+        if (pl.trivial[pos]) continue;
+        col[i] = (int32_t)(std::lower_bound(pl.nontriv_idx.begin(), pl.nontriv_idx.end(),
+                                            (uint32_t)pos) - pl.nontriv_idx.begin());
     }
+    return col;
 }
 
 int rect_valid(uint32_t p0, uint32_t p1, uint32_t q0, uint32_t q1) {
@@ -370,9 +370,7 @@ int rect_valid(uint32_t p0, uint32_t p1, uint32_t q0, uint32_t q1) {
 // The plain and batched sieve share this path.  `rects` are validated.
 int sieve_rects(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes,
                 const std::vector<cuboid_request> &rects, uint64_t surv_cap_total,
-                hipStream_t s, std::vector<std::vector<uint64_t>> *counts_out,
-                std::vector<uint64_t> *pairs_out, std::vector<SurvEntry> *surv_out,
-                uint64_t *n_surv_out) {
+                hipStream_t s, SieveOut *out) {
     std::vector<uint32_t> primes;
     int st = canonical_primes(caller_primes.data(), (uint32_t)caller_primes.size(), &primes);
     if (st) return st;
@@ -451,20 +449,30 @@ int sieve_rects(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes,
             }
         }
     }
-    std::vector<uint64_t> canon((size_t)n_req * nc), pairs(n_req);
-    uint64_t nsurv = 0;
-    HIPCHK(hipMemcpyAsync(canon.data(), ctx->counts.p, canon.size() * 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(pairs.data(), ctx->pairs.p, pairs.size() * 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(&nsurv, ctx->surv_n.p, 8, hipMemcpyDeviceToHost, s));
+    // results through pinned staging: counts, pairs, survivor count
+    const size_t ncount = (size_t)n_req * nc;
+    HIPCHK(ctx->result_stage.ensure((ncount + n_req + 1) * 8));
+    uint64_t *stage = (uint64_t *)ctx->result_stage.p;
+    HIPCHK(hipMemcpyAsync(stage, ctx->counts.p, ncount * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(stage + ncount, ctx->pairs.p, (size_t)n_req * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(stage + ncount + n_req, ctx->surv_n.p, 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    *n_surv_out = nsurv;
-    counts_out->assign(n_req, std::vector<uint64_t>(caller_primes.size(), 0));
-    for (uint32_t i = 0; i < n_req; ++i)
-        map_counts(*pl, caller_primes, canon.data() + (size_t)i * nc, (*counts_out)[i].data());
-    *pairs_out = pairs;
-    surv_out->clear();
+    const uint64_t nsurv = stage[ncount + n_req];
+    const uint32_t np = (uint32_t)caller_primes.size();
+    const std::vector<int32_t> col = count_columns(*pl, caller_primes);
+    out->n_req = n_req;
+    out->n_primes = np;
+    out->n_surv = nsurv;
+    out->counts.assign((size_t)n_req * np, 0);
+    for (uint32_t i = 0; i < n_req; ++i) {
+        const uint64_t *c = stage + (size_t)i * nc;
+        uint64_t *o = out->counts.data() + (size_t)i * np;
+        for (uint32_t j = 0; j < np; ++j) o[j] = col[j] < 0 ? 0 : c[col[j]];
+    }
+    out->pairs.assign(stage + ncount, stage + ncount + n_req);
+    out->surv.clear();
     if (nsurv > 0 && nsurv <= surv_cap) {
-        st = fetch_survivors(ctx, nsurv, surv_out, s);
+        st = fetch_survivors(ctx, nsurv, &out->surv, s);
         if (st) return st;
     }
     if (ctx->timing) {

@@ -93,7 +93,7 @@ struct cuboid_ctx {
 
     // per-call scratch
     cuboid::DevBuf reqbuf, counts, pairs, surv, surv_tmp, surv_n;
-    cuboid::HostBuf req_stage;
+    cuboid::HostBuf req_stage, result_stage;
 
     // timing
     bool timing = false;
@@ -113,10 +113,16 @@ int build_dense(cuboid_ctx *ctx, Plan *pl, uint32_t K, DenseSet **out);
 int ensure_rows(cuboid_ctx *ctx, uint32_t p_max);
 cuboid_tuning tuning_for(cuboid_ctx *ctx, const std::vector<uint32_t> &primes, const Plan &pl);
 int rect_valid(uint32_t p0, uint32_t p1, uint32_t q0, uint32_t q1);
+// Results of one sieve call over several rectangles.
+struct SieveOut {
+    uint32_t n_req = 0, n_primes = 0;
+    std::vector<uint64_t> counts;   // [n_req][n_primes], caller's prime order
+    std::vector<uint64_t> pairs;    // [n_req]
+    std::vector<SurvEntry> surv;    // all survivors sorted by (request, index), if fetched
+    uint64_t n_surv = 0;            // survivors of the whole call
+};
 int sieve_rects(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes,
                 const std::vector<cuboid_request> &rects, uint64_t surv_cap_total,
-                hipStream_t s, std::vector<std::vector<uint64_t>> *counts_out,
-                std::vector<uint64_t> *pairs_out, std::vector<SurvEntry> *surv_out,
-                uint64_t *n_surv_out);
+                hipStream_t s, SieveOut *out);
 
 }  // namespace cuboid
