@@ -79,6 +79,8 @@ int init_ctx(cuboid_ctx *ctx, int dev) {
     HIPCHK(hipMemcpy(ctx->magic16.p, mg.data(), mg.size() * 4, hipMemcpyHostToDevice));
     HIPCHK(ctx->wheel.ensure(kWheelBytes));
     HIPCHK(launch_wheel((uint64_t *)ctx->wheel.p, ctx->stream));
+    HIPCHK(ctx->patterns.ensure(kPatBytes));
+    HIPCHK(launch_patterns((uint64_t *)ctx->patterns.p, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return CUBOID_OK;
 }

@@ -246,8 +246,10 @@ int ensure_rows(cuboid_ctx *ctx, uint32_t p_max) {
     while (R < p_max) R <<= 1;
     if (R > kResidentRowsMax) R = kResidentRowsMax;
     HIPCHK(ctx->rows.ensure(R * sizeof(RowInfo)));
+    HIPCHK(ctx->nfac.ensure(R));
     HIPCHK(launch_row_info((const uint32_t *)ctx->primes16.p, (const uint32_t *)ctx->magic16.p,
-                           ctx->n16, 1, R, (RowInfo *)ctx->rows.p, ctx->stream));
+                           ctx->n16, 1, R, (RowInfo *)ctx->rows.p, (uint8_t *)ctx->nfac.p,
+                           ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     ctx->rows_R = (uint32_t)R;
     return CUBOID_OK;
@@ -272,21 +274,51 @@ cuboid_tuning tuning_for(cuboid_ctx *ctx, const std::vector<uint32_t> &primes, c
 int launch_reqs(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid_tuning &tun,
                 std::vector<ReqDesc> &reqs, uint32_t slot0, uint64_t surv_cap, hipStream_t s,
                 uint64_t *units_out) {
+    const uint32_t n = (uint32_t)reqs.size();
     uint64_t units = 0;
-    for (auto &r : reqs) {
-        r.nrb = (uint32_t)(((uint64_t)r.p1 - r.p0 + 64) / 64);
+    // requests with enough rows get their rows regrouped by factor count
+    std::vector<uint64_t> row_prefix(n + 1, 0), chunk_prefix(n + 1, 0);
+    for (uint32_t i = 0; i < n; ++i) {
+        ReqDesc &r = reqs[i];
+        const uint64_t rows = (uint64_t)r.p1 - r.p0 + 1;
+        r.nrb = (uint32_t)((rows + 63) / 64);
         r.nwin = (uint32_t)(((uint64_t)r.q1 - r.q0 + 64) / 64);
         r.unit0 = units;
         units += (uint64_t)r.nrb * r.nwin;
+        const bool group = ctx->bucketing && rows >= kBucketMinRows &&
+                           row_prefix[i] + rows <= kMaxOrderRows;
+        row_prefix[i + 1] = row_prefix[i] + (group ? rows : 0);
+        chunk_prefix[i + 1] = chunk_prefix[i] + (group ? (rows + kBucketChunk - 1) / kBucketChunk : 0);
+    }
+    const uint64_t n_order = row_prefix[n], n_chunks = chunk_prefix[n];
+    if (n_order) {
+        HIPCHK(ctx->order.ensure(n_order * 4));
+        for (uint32_t i = 0; i < n; ++i)
+            reqs[i].order = row_prefix[i + 1] > row_prefix[i]
+                                ? (const uint32_t *)ctx->order.p + row_prefix[i] : nullptr;
+    } else {
+        for (auto &r : reqs) r.order = nullptr;
     }
     // staged through pinned memory; the previous user of the staging buffer
     // on this stream has completed once the stream is idle
     HIPCHK(hipStreamSynchronize(s));
-    HIPCHK(ctx->req_stage.ensure(reqs.size() * sizeof(ReqDesc)));
-    memcpy(ctx->req_stage.p, reqs.data(), reqs.size() * sizeof(ReqDesc));
-    HIPCHK(ctx->reqbuf.ensure(reqs.size() * sizeof(ReqDesc)));
-    HIPCHK(hipMemcpyAsync(ctx->reqbuf.p, ctx->req_stage.p, reqs.size() * sizeof(ReqDesc),
-                          hipMemcpyHostToDevice, s));
+    HIPCHK(ctx->req_stage.ensure(n * sizeof(ReqDesc) + 2 * (n + 1) * 8));
+    unsigned char *stage = (unsigned char *)ctx->req_stage.p;
+    memcpy(stage, reqs.data(), n * sizeof(ReqDesc));
+    HIPCHK(ctx->reqbuf.ensure(n * sizeof(ReqDesc)));
+    HIPCHK(hipMemcpyAsync(ctx->reqbuf.p, stage, n * sizeof(ReqDesc), hipMemcpyHostToDevice, s));
+    if (n_order) {
+        uint64_t *pre = (uint64_t *)(stage + n * sizeof(ReqDesc));
+        memcpy(pre, chunk_prefix.data(), (n + 1) * 8);
+        memcpy(pre + n + 1, row_prefix.data(), (n + 1) * 8);
+        HIPCHK(ctx->chunk_prefix.ensure((n + 1) * 8));
+        HIPCHK(ctx->row_prefix.ensure((n + 1) * 8));
+        HIPCHK(hipMemcpyAsync(ctx->chunk_prefix.p, pre, (n + 1) * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(ctx->row_prefix.p, pre + n + 1, (n + 1) * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(launch_bucket_rows((const ReqDesc *)ctx->reqbuf.p, n,
+                                  (const uint64_t *)ctx->chunk_prefix.p, n_chunks,
+                                  (const uint64_t *)ctx->row_prefix.p, (uint32_t *)ctx->order.p, s));
+    }
     SweepParams P;
     memset(&P, 0, sizeof(P));
     P.K = ds.K;
@@ -296,32 +328,45 @@ int launch_reqs(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboi
     P.dense_words = ds.words;
     P.dense_tab = (const uint64_t *)ds.tab.p;
     P.wheel = (const uint64_t *)ctx->wheel.p;
+    P.patterns = (const uint64_t *)ctx->patterns.p;
     P.n_deep = ds.n_deep;
     P.nc = ds.K + ds.n_deep;
     P.deep = (const DeepPrime *)ds.deep.p;
     P.vpool = (const uint8_t *)pl.vpool.p;
     P.ipool = (const uint16_t *)pl.ipool.p;
     P.req = (const ReqDesc *)ctx->reqbuf.p;
-    P.n_req = (uint32_t)reqs.size();
+    P.n_req = n;
     P.req_base = slot0;
     P.n_units = units;
     P.counts = (unsigned long long *)ctx->counts.p + (uint64_t)slot0 * P.nc;
     P.pairs = (unsigned long long *)ctx->pairs.p + slot0;
+    P.n_rep = ctx->n_rep;
+    P.rep_stride_counts = ctx->rep_stride_counts;
+    P.rep_stride_pairs = ctx->rep_stride_pairs;
     P.surv = (SurvEntry *)ctx->surv.p;
     P.surv_cap = surv_cap;
     P.surv_n = (unsigned long long *)ctx->surv_n.p;
     const size_t lds = (size_t)ds.words * 8 + kSweepFixedLds;
     if (lds > ctx->max_lds) return CUBOID_E_LIMIT;
     if (ctx->timing) HIPCHK(hipEventRecord(ctx->ev_sweep0, s));
-    HIPCHK(launch_sweep(P, (int)tun.workgroups, lds, s));
+    uint32_t max_p = 0;
+    for (const auto &r : reqs) max_p = std::max(max_p, r.p1);
+    HIPCHK(launch_sweep(P, (int)tun.workgroups, lds, max_p, s));
     if (ctx->timing) HIPCHK(hipEventRecord(ctx->ev_sweep1, s));
     *units_out = units;
     return CUBOID_OK;
 }
 
 int ensure_scratch(cuboid_ctx *ctx, uint32_t n_req, uint32_t nc, uint64_t surv_cap) {
-    HIPCHK(ctx->counts.ensure((size_t)n_req * nc * 8 + 8));
-    HIPCHK(ctx->pairs.ensure((size_t)n_req * 8 + 8));
+    // counter replicas spread the end-of-wave atomics of one request over
+    // several addresses; as many as fit the budget, at most 64
+    uint32_t rep = 64;
+    while (rep > 1 && (uint64_t)rep * n_req * (nc + 1) * 8 > kReplicaBytes) rep >>= 1;
+    ctx->n_rep = rep;
+    ctx->rep_stride_counts = (uint64_t)n_req * nc;
+    ctx->rep_stride_pairs = n_req;
+    HIPCHK(ctx->counts.ensure((size_t)rep * n_req * nc * 8 + 8));
+    HIPCHK(ctx->pairs.ensure((size_t)rep * n_req * 8 + 8));
     HIPCHK(ctx->surv_n.ensure(8));
     const uint64_t rounded = (surv_cap + 1023) / 1024 * 1024;
     HIPCHK(ctx->surv.ensure(rounded * sizeof(SurvEntry) + sizeof(SurvEntry)));
@@ -330,9 +375,17 @@ int ensure_scratch(cuboid_ctx *ctx, uint32_t n_req, uint32_t nc, uint64_t surv_c
 }
 
 int zero_scratch(cuboid_ctx *ctx, uint32_t n_req, uint32_t nc, hipStream_t s) {
-    HIPCHK(launch_fill_u64((uint64_t *)ctx->counts.p, (uint64_t)n_req * nc, 0, s));
-    HIPCHK(launch_fill_u64((uint64_t *)ctx->pairs.p, n_req, 0, s));
+    HIPCHK(launch_fill_u64((uint64_t *)ctx->counts.p, (uint64_t)ctx->n_rep * n_req * nc, 0, s));
+    HIPCHK(launch_fill_u64((uint64_t *)ctx->pairs.p, (uint64_t)ctx->n_rep * n_req, 0, s));
     HIPCHK(launch_fill_u64((uint64_t *)ctx->surv_n.p, 1, 0, s));
+    return CUBOID_OK;
+}
+
+int reduce_scratch(cuboid_ctx *ctx, uint32_t n_req, uint32_t nc, hipStream_t s) {
+    HIPCHK(launch_reduce_replicas((unsigned long long *)ctx->counts.p, (uint64_t)n_req * nc,
+                                  ctx->n_rep, ctx->rep_stride_counts, s));
+    HIPCHK(launch_reduce_replicas((unsigned long long *)ctx->pairs.p, n_req, ctx->n_rep,
+                                  ctx->rep_stride_pairs, s));
     return CUBOID_OK;
 }
 
@@ -407,6 +460,7 @@ int sieve_rects(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes,
             memset(&d, 0, sizeof(d));
             d.p0 = rects[i].p0; d.p1 = rects[i].p1; d.q0 = rects[i].q0; d.q1 = rects[i].q1;
             d.rows = (const RowInfo *)ctx->rows.p;
+            d.nfac = (const uint8_t *)ctx->nfac.p;
             d.rows_p0 = 1;
             d.ip0 = rects[i].p0;
         }
@@ -426,14 +480,17 @@ int sieve_rects(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes,
             for (uint64_t b0 = rc.p0; b0 <= rc.p1; b0 += kBandRows) {
                 const uint64_t b1 = std::min<uint64_t>(rc.p1, b0 + kBandRows - 1);
                 HIPCHK(ctx->band_rows.ensure((b1 - b0 + 1) * sizeof(RowInfo)));
+                HIPCHK(ctx->band_nfac.ensure(b1 - b0 + 1));
                 HIPCHK(launch_row_info((const uint32_t *)ctx->primes16.p,
                                        (const uint32_t *)ctx->magic16.p, ctx->n16, (uint32_t)b0,
-                                       b1 - b0 + 1, (RowInfo *)ctx->band_rows.p, s));
+                                       b1 - b0 + 1, (RowInfo *)ctx->band_rows.p,
+                                       (uint8_t *)ctx->band_nfac.p, s));
                 std::vector<ReqDesc> reqs(1);
                 ReqDesc &d = reqs[0];
                 memset(&d, 0, sizeof(d));
                 d.p0 = (uint32_t)b0; d.p1 = (uint32_t)b1; d.q0 = rc.q0; d.q1 = rc.q1;
                 d.rows = (const RowInfo *)ctx->band_rows.p;
+                d.nfac = (const uint8_t *)ctx->band_nfac.p;
                 d.rows_p0 = (uint32_t)b0;
                 d.ip0 = rc.p0;
                 uint64_t units = 0;
@@ -449,6 +506,8 @@ int sieve_rects(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes,
             }
         }
     }
+    st = reduce_scratch(ctx, n_req, nc, s);
+    if (st) return st;
     // results through pinned staging: counts, pairs, survivor count
     const size_t ncount = (size_t)n_req * nc;
     HIPCHK(ctx->result_stage.ensure((ncount + n_req + 1) * 8));

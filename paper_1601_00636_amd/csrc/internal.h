@@ -10,15 +10,23 @@ namespace cuboid {
 constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kWavesPerWG = 8;       // sweep workgroup = 512 lanes
 constexpr int kKMax = 12;            // most dense (bit-window) primes per launch
-constexpr int kMaxBigFactors = 7;    // distinct primes >= 11 of a uint32 (11*13*..*31 < 2^32 < that*37)
+constexpr int kMaxBigFactors = 7;    // distinct primes >= 7 of a uint32 (7*11*..*29 < 2^32 < that*31)
 constexpr int kQueueCap = 128;       // per-wave queue of windows that outlive the dense primes
 constexpr int kDeepCounters = 128;   // per-wave LDS counters for the first deep primes
-constexpr int kWheel = 210;          // 2*3*5*7
-constexpr int kWheelSubsets = 16;    // subsets of {2,3,5,7}
+constexpr int kWheel = 30;           // 2*3*5
+constexpr int kWheelSubsets = 9;     // subsets of {2,3,5}, then an all-ones row for idle lanes
+constexpr int kIdleSubset = 8;
+constexpr int kBucketChunk = 8192;   // rows regrouped by factor count within each chunk
+// Multiple patterns: for each prime l in 7..61, l entries (entry d, the
+// distance from a window's first column to the next multiple of l, has bit j
+// set for every j = d mod l, j < 64); then 65 entries 1<<j (j < 64) and 0,
+// used by primes >= 64 whose next multiple is at distance min(d, 64).
+constexpr int kPatSmall = 491;       // 7 + 11 + 13 + ... + 61
+constexpr int kPatEntries = kPatSmall + 65;
 
 // Distinct prime factors of one row coordinate p.
-//   meta bits 0..3: which of 2, 3, 5, 7 divide p; bits 4..7: number of f[] used.
-//   f[]: the distinct prime factors >= 11 of p, ascending.
+//   meta bits 0..2: which of 2, 3, 5 divide p; bits 4..7: number of f[] used.
+//   f[]: the distinct prime factors >= 7 of p, ascending.
 struct RowInfo {
     uint32_t meta;
     uint32_t f[kMaxBigFactors];
@@ -43,6 +51,8 @@ struct ReqDesc {
     const RowInfo *rows;   // row info for p at rows[p - rows_p0]
     uint32_t rows_p0;
     uint32_t ip0;          // p0 of the caller's rectangle (survivor indices)
+    const uint32_t *order; // rows in processing order, or null for p0, p0 + 1, ...
+    const uint8_t *nfac;   // number of f[] of p at nfac[p - rows_p0]
 };
 
 struct SurvEntry {
@@ -59,7 +69,8 @@ struct SweepParams {
     uint32_t doff[kKMax];                // LDS byte offset of that prime's window table
     uint32_t dense_words;                // 64-bit words of all window tables
     const uint64_t *dense_tab;           // window tables in HBM (copied to LDS)
-    const uint64_t *wheel;               // 16 x 210 coprimality windows (copied to LDS)
+    const uint64_t *wheel;               // 9 x 30 coprimality windows (copied to LDS)
+    const uint64_t *patterns;            // multiple patterns (copied to LDS)
     uint32_t n_deep;
     uint32_t nc;                         // counters per request = K + n_deep
     const DeepPrime *deep;
@@ -69,8 +80,12 @@ struct SweepParams {
     uint32_t n_req;
     uint32_t req_base;                   // added to request numbers in survivor entries
     uint64_t n_units;
-    unsigned long long *counts;          // [n_req][nc], canonical ascending order
-    unsigned long long *pairs;           // [n_req]
+    unsigned long long *counts;          // [n_rep][..][nc], canonical ascending order
+    unsigned long long *pairs;           // [n_rep][..]
+    uint32_t n_rep;                      // counter replicas (power of two), by wave
+    uint32_t pad1;
+    uint64_t rep_stride_counts;          // elements between replicas
+    uint64_t rep_stride_pairs;
     SurvEntry *surv;
     unsigned long long surv_cap;
     unsigned long long *surv_n;
@@ -80,7 +95,8 @@ struct SweepParams {
 constexpr size_t kWheelBytes = (size_t)kWheelSubsets * kWheel * 8;
 constexpr size_t kQueueEntryBytes = 16;
 constexpr size_t kPerWaveBytes = kQueueCap * kQueueEntryBytes + kDeepCounters * 4;
-constexpr size_t kSweepFixedLds = kWheelBytes + kWavesPerWG * kPerWaveBytes;
+constexpr size_t kPatBytes = (size_t)kPatEntries * 8;
+constexpr size_t kSweepFixedLds = kWheelBytes + kPatBytes + kWavesPerWG * kPerWaveBytes;
 
 // ---- kernel launchers (kernels_*.hip) ----
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
@@ -103,9 +119,21 @@ hipError_t launch_dense_windows(const uint32_t *pr, const uint32_t *voff, const 
                                 uint64_t total, const uint8_t *vpool, const uint16_t *ipool,
                                 uint64_t *out, hipStream_t s);
 hipError_t launch_wheel(uint64_t *out, hipStream_t s);
+hipError_t launch_patterns(uint64_t *out, hipStream_t s);
+uint32_t pattern_offset(uint32_t l);   // entry offset of prime l's patterns (l in 7..61)
 hipError_t launch_row_info(const uint32_t *primes16, const uint32_t *magic16, uint32_t n16,
-                           uint32_t pstart, uint64_t count, RowInfo *out, hipStream_t s);
-hipError_t launch_sweep(const SweepParams &P, int grid, size_t lds_bytes, hipStream_t s);
+                           uint32_t pstart, uint64_t count, RowInfo *out, uint8_t *nfac,
+                           hipStream_t s);
+// regroup each request's rows, chunk by chunk, by number of factors >= 7
+hipError_t launch_bucket_rows(const ReqDesc *req, uint32_t n_req, const uint64_t *chunk_prefix,
+                              uint64_t n_chunks, const uint64_t *row_prefix, uint32_t *order,
+                              hipStream_t s);
+// dst[i] = sum of n_rep replicas src[r * stride + i], in place on replica 0
+hipError_t launch_reduce_replicas(unsigned long long *buf, uint64_t n, uint32_t n_rep,
+                                  uint64_t stride, hipStream_t s);
+// max_p: the largest row coordinate of the launch (selects the factor slots)
+hipError_t launch_sweep(const SweepParams &P, int grid, size_t lds_bytes, uint32_t max_p,
+                        hipStream_t s);
 hipError_t sweep_max_lds(size_t *bytes);
 // sorts n <= cap entries (n read from device) ascending by (req, idx) into out
 hipError_t launch_sort_surv(SurvEntry *a, SurvEntry *tmp, const unsigned long long *n_dev,

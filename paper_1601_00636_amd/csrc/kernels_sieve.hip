@@ -56,10 +56,17 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
 // x mod d for a per-lane divisor d >= 1 (used at segment setup only)
 __device__ __forceinline__ uint32_t mod_var(uint32_t x, uint32_t d) { return x % d; }
 
+// entry offset of the multiple patterns of a prime l in 7..61 (others unused)
+__constant__ uint16_t c_pat_off[64] = {
+    0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 7, 0, 18, 0, 0, 0, 31, 0, 48, 0, 0, 0, 67, 0, 0, 0, 0, 0, 90,
+    0, 119, 0, 0, 0, 0, 0, 150, 0, 0, 0, 187, 0, 228, 0, 0, 0, 271, 0, 0, 0, 0, 0, 318, 0, 0, 0, 0,
+    0, 371, 0, 430, 0, 0};
+
 // Tests the pairs of one queued window against the deep primes, in ascending
 // order; counts the first rejecting prime, appends unrejected pairs.
 __device__ __forceinline__ void deep_window(const SweepParams &P, const QEntry e, uint32_t ri,
-                                            const ReqDesc &R, uint32_t *dcnt) {
+                                            const ReqDesc &R, uint32_t *dcnt,
+                                            unsigned long long *cnt_rep) {
     uint64_t mask = e.mask;
     const uint64_t width = (uint64_t)R.q1 - R.q0 + 1;
     while (mask) {
@@ -76,7 +83,7 @@ __device__ __forceinline__ void deep_window(const SweepParams &P, const QEntry e
                 if (i < kDeepCounters)
                     atomicAdd(&dcnt[i], 1u);
                 else
-                    atomicAdd(&P.counts[(uint64_t)ri * P.nc + P.K + i], 1ull);
+                    atomicAdd(&cnt_rep[(uint64_t)ri * P.nc + P.K + i], 1ull);
                 rejected = true;
                 break;
             }
@@ -94,29 +101,42 @@ __device__ __forceinline__ void deep_window(const SweepParams &P, const QEntry e
     }
 }
 
-template <int KD>
+__device__ __forceinline__ uint64_t lds64(const unsigned char *base, uint32_t byte_off) {
+    return *(const uint64_t *)(base + byte_off);
+}
+
+constexpr uint32_t kFlushWindows = 1u << 19;   // per-lane u32 counters stay below 2^31
+
+// KD dense primes; MF factor slots (enough for every row of the launch)
+template <int KD, int MF>
 __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepParams P) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid >> 6;
+    // LDS: dense window tables | wheel | multiple patterns | per-wave queue + counters
     uint64_t *sdense = (uint64_t *)smem;
     uint64_t *swheel = sdense + P.dense_words;
-    unsigned char *wave_area = (unsigned char *)(swheel + kWheelSubsets * kWheel) +
-                               (size_t)wv * kPerWaveBytes;
+    uint64_t *spat = swheel + kWheelSubsets * kWheel;
+    unsigned char *wave_area = (unsigned char *)(spat + kPatEntries) + (size_t)wv * kPerWaveBytes;
     QEntry *queue = (QEntry *)wave_area;
     uint32_t *dcnt = (uint32_t *)(wave_area + kQueueCap * sizeof(QEntry));
 
     for (uint32_t i = tid; i < P.dense_words; i += blockDim.x) sdense[i] = P.dense_tab[i];
     for (uint32_t i = tid; i < kWheelSubsets * kWheel; i += blockDim.x) swheel[i] = P.wheel[i];
+    for (uint32_t i = tid; i < (uint32_t)kPatEntries; i += blockDim.x) spat[i] = P.patterns[i];
     for (uint32_t i = lane; i < kDeepCounters; i += kWave) dcnt[i] = 0;
     __syncthreads();
 
     const uint32_t wheel_byte = P.dense_words * 8;
+    const uint32_t pat_byte = wheel_byte + kWheelSubsets * kWheel * 8;
     const uint64_t nwaves = (uint64_t)gridDim.x * kWavesPerWG;
     const uint64_t w = (uint64_t)blockIdx.x * kWavesPerWG + wv;
     const uint64_t qd = P.n_units / nwaves, rd = P.n_units % nwaves;
     uint64_t u = uni64(qd * w + (rd * w) / nwaves);
     const uint64_t uend = uni64(qd * (w + 1) + (rd * (w + 1)) / nwaves);
     if (u >= uend) return;
+    const uint32_t rep = uni((uint32_t)(w & (P.n_rep - 1)));
+    unsigned long long *cnt_rep = P.counts + (uint64_t)rep * P.rep_stride_counts;
+    unsigned long long *pairs_rep = P.pairs + (uint64_t)rep * P.rep_stride_pairs;
 
     // request holding unit u: last i with req[i].unit0 <= u
     uint32_t ri;
@@ -133,33 +153,33 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
     for (int k = 0; k <= KD; ++k) cnt[k] = 0;
     uint32_t npairs = 0;
     uint32_t qn = 0;            // queued windows (wave-uniform)
-    uint32_t since_flush = 0;   // windows since counters were flushed
+    uint32_t since_flush = 0;   // windows since counters were flushed (wave-uniform)
 
     auto drain = [&](uint32_t n, const ReqDesc &R) {
         __builtin_amdgcn_wave_barrier();
-        if (lane < n) deep_window(P, queue[qn - n + lane], ri, R, dcnt);
+        if (lane < n) deep_window(P, queue[qn - n + lane], ri, R, dcnt, cnt_rep);
         __builtin_amdgcn_wave_barrier();
-        qn -= n;
+        qn = uni(qn - n);
     };
 
     auto flush = [&](const ReqDesc &R) {
-        while (qn) drain(qn < kWave ? qn : kWave, R);
+        while (qn) drain(qn < (uint32_t)kWave ? qn : (uint32_t)kWave, R);
         const uint64_t cbase = (uint64_t)ri * P.nc;
 #pragma unroll
         for (int k = 0; k < KD; ++k) {
             const uint32_t s = wave_sum(cnt[k]);
-            if (lane == 0 && s) atomicAdd(&P.counts[cbase + k], (unsigned long long)s);
+            if (lane == 0 && s) atomicAdd(&cnt_rep[cbase + k], (unsigned long long)s);
             cnt[k] = 0;
         }
         const uint32_t s = wave_sum(npairs);
-        if (lane == 0 && s) atomicAdd(&P.pairs[ri], (unsigned long long)s);
+        if (lane == 0 && s) atomicAdd(&pairs_rep[ri], (unsigned long long)s);
         npairs = 0;
         __builtin_amdgcn_wave_barrier();
         const uint32_t ndc = P.n_deep < kDeepCounters ? P.n_deep : kDeepCounters;
         for (uint32_t i = lane; i < ndc; i += kWave) {
             const uint32_t v = dcnt[i];
             if (v) {
-                atomicAdd(&P.counts[cbase + KD + i], (unsigned long long)v);
+                atomicAdd(&cnt_rep[cbase + KD + i], (unsigned long long)v);
                 dcnt[i] = 0;
             }
         }
@@ -183,20 +203,22 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
         const uint32_t win0 = uni((uint32_t)(local % R.nwin));
         uint64_t seg_end = R.unit0 + (uint64_t)(rb + 1) * R.nwin;
         if (seg_end > uend) seg_end = uend;
-        const uint32_t nw = uni((uint32_t)(seg_end - u));
+        uint32_t nw = uni((uint32_t)(seg_end - u));
+        if (nw > kFlushWindows - since_flush) nw = uni(kFlushWindows - since_flush);
 
-        // ---- segment setup: 64 rows, starting column qs ----
-        const uint64_t p64 = (uint64_t)R.p0 + (uint64_t)rb * kWave + lane;
-        const bool valid = p64 <= R.p1;
-        const uint32_t p = valid ? (uint32_t)p64 : 1u;
+        // ---- segment setup: 64 rows (one per lane), starting column qs ----
+        const uint64_t nrows = (uint64_t)R.p1 - R.p0 + 1;
+        const uint64_t ridx = (uint64_t)rb * kWave + lane;
+        const bool valid = ridx < nrows;
+        uint32_t p = 0;
         RowInfo rinfo;
+        rinfo.meta = kIdleSubset;
+        for (int f = 0; f < kMaxBigFactors; ++f) rinfo.f[f] = 0;
         if (valid) {
+            p = R.order ? R.order[ridx] : R.p0 + (uint32_t)ridx;
             rinfo = R.rows[p - R.rows_p0];
-        } else {
-            rinfo.meta = 0;
-            for (int f = 0; f < kMaxBigFactors; ++f) rinfo.f[f] = 0;
+            rinfo.meta &= ~8u;
         }
-        const uint64_t rowmask = valid ? ~0ull : 0ull;
         const uint32_t nf = (rinfo.meta >> 4) & 15;
         const uint32_t nfmax = uni(wave_max(nf));
         const uint32_t wheel_lane = wheel_byte + (rinfo.meta & 15) * (kWheel * 8);
@@ -208,57 +230,60 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
             lb[k] = P.doff[k] + modr(p, P.dr[k], P.dm[k]) * P.dr[k] * 8;
             ok[k] = uni(modr(qs, P.dr[k], P.dm[k]));
         }
-        uint32_t o210 = uni(qs % kWheel);
+        uint32_t o30 = uni(qs % kWheel);
 
-        uint32_t fo[kMaxBigFactors], fd[kMaxBigFactors], fl[kMaxBigFactors];
-        uint64_t fp[kMaxBigFactors];
+        // factor l of p: fo = distance from the window start to the next
+        // multiple of l, fd = 64 mod l (64 for l >= 64), fb = LDS byte
+        // offset of its pattern entries
+        uint32_t fo[MF], fd[MF], fl[MF], fb[MF];
 #pragma unroll
-        for (int f = 0; f < kMaxBigFactors; ++f) {
-            if ((uint32_t)f < nf) {
+        for (int f = 0; f < MF; ++f) {
+            fl[f] = 0; fd[f] = 0; fo[f] = 0xffffffffu;
+            fb[f] = pat_byte + kPatSmall * 8;
+            if ((uint32_t)f < nfmax && (uint32_t)f < nf) {
                 const uint32_t l = rinfo.f[f];
                 const uint32_t rem = mod_var(qs, l);
                 fl[f] = l;
-                fo[f] = rem ? l - rem : 0;             // distance to the next multiple
-                fd[f] = l > kWave ? (uint32_t)kWave : (uint32_t)kWave % l;
-                uint64_t pat = 0;
-                for (uint32_t j = 0; j < (uint32_t)kWave; j += l) pat |= 1ull << j;
-                fp[f] = pat;
-            } else {
-                fl[f] = 0; fd[f] = 0; fo[f] = 0xffffffffu; fp[f] = 0;
+                fo[f] = rem ? l - rem : 0;
+                fd[f] = l > (uint32_t)kWave ? (uint32_t)kWave : (uint32_t)kWave % l;
+                if (l < (uint32_t)kWave) fb[f] = pat_byte + c_pat_off[l] * 8;
             }
         }
 
         // ---- windows ----
         for (uint32_t k = 0; k < nw; ++k) {
             const uint32_t qb = qs + k * kWave;
-            const uint32_t rem = R.q1 - qb + 1;
-            uint64_t alive = (rem >= (uint32_t)kWave ? ~0ull : ((1ull << rem) - 1)) & rowmask;
-            uint64_t nc = *(const uint64_t *)(smem + wheel_lane + o210 * 8);
+            uint64_t nc = lds64(smem, wheel_lane + o30 * 8);
 #pragma unroll
-            for (int f = 0; f < kMaxBigFactors; ++f) {
+            for (int f = 0; f < MF; ++f) {
                 if ((uint32_t)f < nfmax) {
-                    nc |= fo[f] < (uint32_t)kWave ? (fp[f] << fo[f]) : 0ull;
+                    const uint32_t idx = fo[f] < (uint32_t)kWave ? fo[f] : (uint32_t)kWave;
+                    nc |= lds64(smem, fb[f] + idx * 8);
                     const uint32_t t = fo[f] - fd[f];
                     const uint32_t t2 = t + fl[f];
                     fo[f] = t < t2 ? t : t2;
                 }
             }
-            alive &= ~nc;
+            uint64_t alive = ~nc;
+            const uint32_t rem = R.q1 - qb + 1;
+            if (rem < (uint32_t)kWave) alive &= (1ull << rem) - 1;
             if (qb == 1) {
                 if (p == 1) alive &= ~1ull;   // (1, 1) is coprime but p = q
             }
-            npairs += __popcll(alive);
+            npairs = __builtin_popcount((uint32_t)alive) + npairs;
+            npairs = __builtin_popcount((uint32_t)(alive >> 32)) + npairs;
 #pragma unroll
             for (int d = 0; d < KD; ++d) {
-                const uint64_t win = *(const uint64_t *)(smem + lb[d] + ok[d] * 8);
+                const uint64_t win = lds64(smem, lb[d] + ok[d] * 8);
                 const uint64_t hit = alive & win;
-                cnt[d] += __popcll(hit);
+                cnt[d] = __builtin_popcount((uint32_t)hit) + cnt[d];
+                cnt[d] = __builtin_popcount((uint32_t)(hit >> 32)) + cnt[d];
                 alive ^= hit;
                 ok[d] += P.dstep[d];
                 if (ok[d] >= P.dr[d]) ok[d] -= P.dr[d];
             }
-            o210 += kWave;
-            if (o210 >= (uint32_t)kWheel) o210 -= kWheel;
+            o30 += kWave % kWheel;
+            if (o30 >= (uint32_t)kWheel) o30 -= kWheel;
 
             const uint64_t bal = __ballot(alive != 0);
             if (bal) {
@@ -271,13 +296,12 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
                 qn = uni(qn + (uint32_t)__popcll(bal));
                 if (qn >= (uint32_t)kWave) drain(kWave, R);
             }
-            if (++since_flush >= (1u << 19)) flush(R);
         }
-        u = seg_end;
-        if (u >= uend) flush(R);
+        u += nw;
+        since_flush = uni(since_flush + nw);
+        if (u >= uend || since_flush >= kFlushWindows) flush(R);
     }
 }
-
 
 // ---- survivor sort: block bitonic sort of 1024, then rank-based merges ----
 
@@ -348,20 +372,28 @@ __global__ void merge_pass_kernel(const SurvEntry *src, SurvEntry *dst,
 
 }  // namespace
 
-hipError_t launch_sweep(const SweepParams &P, int grid, size_t lds_bytes, hipStream_t s) {
+hipError_t launch_sweep(const SweepParams &P, int grid, size_t lds_bytes, uint32_t max_p,
+                        hipStream_t s) {
     if (P.K > (uint32_t)kKMax) return hipErrorInvalidValue;
     if (P.n_units == 0) return hipSuccess;
     const dim3 g(grid), b(kWave * kWavesPerWG);
+    // factor slots: a row below 7*11*13*17*19 has at most 4 distinct primes
+    // >= 7, below 7*11*13*17*19*23 at most 5, any uint32 at most 7
+    const int mf = max_p < 323323u ? 4 : (max_p < 7436429u ? 5 : 7);
+#define CUBOID_SWEEP_K(k)                                                                      \
+    case k:                                                                                    \
+        if (mf == 4) hipLaunchKernelGGL((sweep_kernel<k, 4>), g, b, lds_bytes, s, P);           \
+        else if (mf == 5) hipLaunchKernelGGL((sweep_kernel<k, 5>), g, b, lds_bytes, s, P);      \
+        else hipLaunchKernelGGL((sweep_kernel<k, 7>), g, b, lds_bytes, s, P);                   \
+        break;
     switch (P.K) {
-#define CUBOID_SWEEP_CASE(k) \
-    case k: hipLaunchKernelGGL(sweep_kernel<k>, g, b, lds_bytes, s, P); break;
-        CUBOID_SWEEP_CASE(0) CUBOID_SWEEP_CASE(1) CUBOID_SWEEP_CASE(2) CUBOID_SWEEP_CASE(3)
-        CUBOID_SWEEP_CASE(4) CUBOID_SWEEP_CASE(5) CUBOID_SWEEP_CASE(6) CUBOID_SWEEP_CASE(7)
-        CUBOID_SWEEP_CASE(8) CUBOID_SWEEP_CASE(9) CUBOID_SWEEP_CASE(10) CUBOID_SWEEP_CASE(11)
-        CUBOID_SWEEP_CASE(12)
-#undef CUBOID_SWEEP_CASE
+        CUBOID_SWEEP_K(0) CUBOID_SWEEP_K(1) CUBOID_SWEEP_K(2) CUBOID_SWEEP_K(3)
+        CUBOID_SWEEP_K(4) CUBOID_SWEEP_K(5) CUBOID_SWEEP_K(6) CUBOID_SWEEP_K(7)
+        CUBOID_SWEEP_K(8) CUBOID_SWEEP_K(9) CUBOID_SWEEP_K(10) CUBOID_SWEEP_K(11)
+        CUBOID_SWEEP_K(12)
         default: return hipErrorInvalidValue;
     }
+#undef CUBOID_SWEEP_K
     return hipGetLastError();
 }
 

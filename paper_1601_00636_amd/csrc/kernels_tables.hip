@@ -156,27 +156,50 @@ __global__ void dense_windows_kernel(const uint32_t *pr, const uint32_t *voff,
     }
 }
 
-// Coprimality wheel: entry s*210 + o has bit j set when o + j is divisible by
-// one of the primes of subset s of {2, 3, 5, 7} (bit 0 = 2, ..., bit 3 = 7).
+// Coprimality wheel: entry s*30 + o has bit j set when o + j is divisible by
+// one of the primes of subset s of {2, 3, 5} (bit 0 = 2, bit 1 = 3, bit 2 = 5);
+// row 8 is all ones (a lane without a row keeps no pairs).
 __global__ void wheel_kernel(uint64_t *out) {
     const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= kWheelSubsets * kWheel) return;
     const uint32_t s = e / kWheel, o = e % kWheel;
-    const uint32_t sp[4] = {2, 3, 5, 7};
+    if (s == kIdleSubset) { out[e] = ~0ull; return; }
+    const uint32_t sp[3] = {2, 3, 5};
     uint64_t w = 0;
     for (uint32_t j = 0; j < 64; ++j) {
         bool hit = false;
-        for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < 3; ++k)
             if (((s >> k) & 1) && (o + j) % sp[k] == 0) hit = true;
         if (hit) w |= 1ull << j;
     }
     out[e] = w;
 }
 
+__constant__ uint32_t kPatPrimes[15] = {7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47, 53, 59, 61};
+
+// Multiple patterns (see kPatSmall): prime l's entry d (the distance from a
+// window's first column to the next multiple of l) has bit j for j = d mod l.
+__global__ void patterns_kernel(uint64_t *out) {
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (uint32_t)kPatEntries) return;
+    if (e >= (uint32_t)kPatSmall) {
+        const uint32_t j = e - kPatSmall;
+        out[e] = j < 64 ? (1ull << j) : 0ull;
+        return;
+    }
+    uint32_t base = 0, i = 0;
+    while (base + kPatPrimes[i] <= e) { base += kPatPrimes[i]; ++i; }
+    const uint32_t l = kPatPrimes[i], d = e - base;
+    uint64_t w = 0;
+    for (uint32_t j = 0; j < 64; ++j)
+        if (j % l == d) w |= 1ull << j;
+    out[e] = w;
+}
+
 // Distinct prime factors of p = pstart + g by trial division with the primes
 // below 2^16 (enough for any uint32).  primes16 starts 2, 3, 5, 7, 11, ...
 __global__ void row_info_kernel(const uint32_t *primes16, const uint32_t *magic16, uint32_t n16,
-                                uint32_t pstart, uint64_t count, RowInfo *out) {
+                                uint32_t pstart, uint64_t count, RowInfo *out, uint8_t *nfac) {
     for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < count;
          g += (uint64_t)gridDim.x * blockDim.x) {
         uint32_t x = pstart + (uint32_t)g;
@@ -191,17 +214,60 @@ __global__ void row_info_kernel(const uint32_t *primes16, const uint32_t *magic1
             uint32_t rem;
             uint32_t qt = divr(x, l, m, &rem);
             if (rem) continue;
-            if (i < 4) ri.meta |= 1u << i; else ri.f[nf++] = l;
+            if (i < 3) ri.meta |= 1u << i; else ri.f[nf++] = l;
             do { x = qt; qt = divr(x, l, m, &rem); } while (rem == 0);
         }
         if (x > 1) {
             // remaining cofactor is prime
             if (x == 2) ri.meta |= 1; else if (x == 3) ri.meta |= 2;
-            else if (x == 5) ri.meta |= 4; else if (x == 7) ri.meta |= 8;
+            else if (x == 5) ri.meta |= 4;
             else ri.f[nf++] = x;
         }
         ri.meta |= nf << 4;
         out[g] = ri;
+        nfac[g] = (uint8_t)nf;
+    }
+}
+
+// One block per chunk of kBucketChunk rows of a request: the chunk's rows are
+// written to `order` grouped by their number of factors >= 7, so that the 64
+// rows of a wavefront tend to share that number.
+__global__ void __launch_bounds__(256) bucket_rows_kernel(const ReqDesc *req, uint32_t n_req,
+                                                          const uint64_t *chunk_prefix,
+                                                          const uint64_t *row_prefix,
+                                                          uint32_t *order) {
+    __shared__ uint32_t cnt[kMaxBigFactors + 1];
+    const uint64_t b = blockIdx.x;
+    const uint32_t i = find_segment(chunk_prefix, n_req, b);
+    const ReqDesc R = req[i];
+    const uint64_t rows = (uint64_t)R.p1 - R.p0 + 1;
+    const uint64_t r0 = (b - chunk_prefix[i]) * kBucketChunk;
+    const uint64_t r1 = r0 + kBucketChunk < rows ? r0 + kBucketChunk : rows;
+    if (threadIdx.x <= (unsigned)kMaxBigFactors) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x)
+        atomicAdd(&cnt[R.nfac[R.p0 + (uint32_t)r - R.rows_p0]], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int k = 0; k <= kMaxBigFactors; ++k) { const uint32_t c = cnt[k]; cnt[k] = acc; acc += c; }
+    }
+    __syncthreads();
+    uint32_t *dst = order + row_prefix[i] + r0;
+    for (uint64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+        const uint32_t p = R.p0 + (uint32_t)r;
+        const uint32_t pos = atomicAdd(&cnt[R.nfac[p - R.rows_p0]], 1u);
+        dst[pos] = p;
+    }
+}
+
+__global__ void reduce_replicas_kernel(unsigned long long *buf, uint64_t n, uint32_t n_rep,
+                                       uint64_t stride) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        unsigned long long acc = buf[i];
+        for (uint32_t r = 1; r < n_rep; ++r) acc += buf[r * stride + i];
+        buf[i] = acc;
     }
 }
 
@@ -276,10 +342,44 @@ hipError_t launch_wheel(uint64_t *out, hipStream_t s) {
 }
 
 hipError_t launch_row_info(const uint32_t *primes16, const uint32_t *magic16, uint32_t n16,
-                           uint32_t pstart, uint64_t count, RowInfo *out, hipStream_t s) {
+                           uint32_t pstart, uint64_t count, RowInfo *out, uint8_t *nfac,
+                           hipStream_t s) {
     if (!count) return hipSuccess;
     hipLaunchKernelGGL(row_info_kernel, dim3(grid_for(count)), dim3(kBlock), 0, s, primes16,
-                       magic16, n16, pstart, count, out);
+                       magic16, n16, pstart, count, out, nfac);
+    return hipGetLastError();
+}
+
+hipError_t launch_patterns(uint64_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(patterns_kernel, dim3((kPatEntries + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                       s, out);
+    return hipGetLastError();
+}
+
+uint32_t pattern_offset(uint32_t l) {
+    static const uint32_t pr[15] = {7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47, 53, 59, 61};
+    uint32_t base = 0;
+    for (uint32_t i = 0; i < 15; ++i) {
+        if (pr[i] == l) return base;
+        base += pr[i];
+    }
+    return kPatSmall;   // the single-bit entries
+}
+
+hipError_t launch_bucket_rows(const ReqDesc *req, uint32_t n_req, const uint64_t *chunk_prefix,
+                              uint64_t n_chunks, const uint64_t *row_prefix, uint32_t *order,
+                              hipStream_t s) {
+    if (!n_chunks) return hipSuccess;
+    hipLaunchKernelGGL(bucket_rows_kernel, dim3((unsigned)n_chunks), dim3(256), 0, s, req, n_req,
+                       chunk_prefix, row_prefix, order);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_replicas(unsigned long long *buf, uint64_t n, uint32_t n_rep,
+                                  uint64_t stride, hipStream_t s) {
+    if (!n || n_rep <= 1) return hipSuccess;
+    hipLaunchKernelGGL(reduce_replicas_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, buf, n, n_rep,
+                       stride);
     return hipGetLastError();
 }
 

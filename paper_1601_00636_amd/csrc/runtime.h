@@ -19,6 +19,9 @@ constexpr uint32_t kResidentRowsMax = 1u << 24;       // rows with resident fact
 constexpr uint64_t kBandRows = 1u << 22;              // rows per band beyond that
 constexpr uint64_t kMaxSurvScratch = 1ull << 26;      // survivors held on the device per call
 constexpr uint32_t kDefaultLdsBudget = 32 * 1024;     // LDS bytes for dense window tables
+constexpr uint64_t kMaxOrderRows = 1ull << 27;        // rows regrouped per call
+constexpr uint64_t kBucketMinRows = 128;              // smaller requests keep their row order
+constexpr uint64_t kReplicaBytes = 32ull << 20;       // budget for counter replicas
 
 // Grow-only device allocation.
 struct DevBuf {
@@ -81,18 +84,23 @@ struct cuboid_ctx {
     // constant tables
     cuboid::DevBuf primes16, magic16;   // primes below 2^16 and floor(2^32 / p)
     uint32_t n16 = 0;
-    cuboid::DevBuf wheel;               // 16 x 210 coprimality windows
+    cuboid::DevBuf wheel;               // 9 x 30 coprimality windows
+    cuboid::DevBuf patterns;            // multiple patterns of the factors >= 7
 
     // resident factor lists of rows 1..rows_R
-    cuboid::DevBuf rows;
+    cuboid::DevBuf rows, nfac;
     uint32_t rows_R = 0;
-    cuboid::DevBuf band_rows;
+    cuboid::DevBuf band_rows, band_nfac;
 
     std::map<std::vector<uint32_t>, std::unique_ptr<cuboid::Plan>> plans;
     std::map<std::vector<uint32_t>, cuboid_tuning> tunings;
 
     // per-call scratch
     cuboid::DevBuf reqbuf, counts, pairs, surv, surv_tmp, surv_n;
+    cuboid::DevBuf order, chunk_prefix, row_prefix;   // row regrouping
+    uint32_t n_rep = 1;                 // counter replicas of the current call
+    uint64_t rep_stride_counts = 0, rep_stride_pairs = 0;
+    bool bucketing = true;
     cuboid::HostBuf req_stage, result_stage;
 
     // timing
