@@ -78,6 +78,32 @@ def run_cpu_baseline(reqs, primes, stride):
                        "pairs) in %.1f s; tables excluded" % (stride, len(sample), pairs, dt))
 
 
+def run_served(cb, wl, ctx, primes, seconds):
+    """Replay the seeded Poisson stream (2000 requests/s, areas log-uniform in
+    [1e3, 1e9]) against the server; latency = completion - submission."""
+    stream = wl.served_stream(duration=seconds, max_requests=int(2000 * seconds))
+    srv = cb.cuboid_server_start(ctx, primes)
+    try:
+        t0 = time.perf_counter()
+        tickets = []
+        for at, rect in stream:
+            while time.perf_counter() - t0 < at:
+                pass
+            tickets.append(cb.cuboid_server_submit(srv, rect))
+        out = [cb.cuboid_server_poll(srv, t, len(primes), cap=4096) for t in tickets]
+        stats = cb.cuboid_server_stats_get(srv)
+    finally:
+        cb.cuboid_server_stop(srv)
+    lat = np.array([r["latency_ns"] for r in out], dtype=np.float64) / 1e6
+    pairs = sum(r["n_pairs"] for r in out)
+    span = (max(r["done_ns"] for r in out) - min(r["submit_ns"] for r in out)) / 1e9
+    return {"requests": len(out), "offered_rate_per_s": 2000, "seconds": seconds,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "max_ms": float(lat.max()), "coprime_pairs": pairs,
+            "pairs_per_s_over_span": pairs / span, "launches": stats["launches"],
+            "max_admitted": stats["max_admitted"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +112,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=64)
+    ap.add_argument("--served-seconds", type=float, default=10.0)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -203,6 +230,9 @@ def main():
                                       "ms": float(np.median(reps)) * 1e3,
                                       "sweep_ms": t3["sweep_ms"], "n_pairs": r3["n_pairs"],
                                       "sweep_pairs_per_s": r3["n_pairs"] / (t3["sweep_ms"] * 1e-3)}
+
+    if not args.no_extras and args.served_seconds > 0:
+        res["extras"]["served"] = run_served(cb, wl, ctx, primes, args.served_seconds)
 
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = run_cpu_baseline(reqs, primes, args.cpu_stride)

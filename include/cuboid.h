@@ -21,7 +21,8 @@
  *     (section 5: 1 = already running / busy, 6 = tables not loaded).
  *   - Buffers: all pointers are HOST memory owned by the caller, unless a
  *     parameter says "device".  The library never keeps a caller pointer after
- *     the call returns (except the server, see cuboid_server_submit).
+ *     the call returns (the server holds each ticket's results itself until
+ *     they are polled).
  *   - The library owns the context, its device tables and device scratch.
  *   - `hip_stream` is a hipStream_t (as void*); NULL means the context's own
  *     stream.  Calls that return host results synchronise that stream before
@@ -207,6 +208,67 @@ typedef struct cuboid_result {
 int cuboid_sieve_batch(cuboid_ctx *ctx, const cuboid_request *req, uint32_t n_req,
                        const uint32_t *primes, uint32_t n_primes,
                        cuboid_result *res, void *hip_stream);
+
+/* ------------------------------------------------------------------ served */
+
+/*
+ * A request server over one context and one prime list: a worker thread
+ * keeps the unsolvability tables resident and runs continuous batching.
+ * Requests submitted while others are on the GPU are admitted as counter
+ * slots and device memory free up and join the next launch; every launch
+ * takes at most `max_launch_units` 64 x 64 units from the requests admitted
+ * to its stream (a large request spans several launches), so small requests
+ * are not held behind large ones.  Each request's results are bit-exact those
+ * of cuboid_sieve_range alone.
+ */
+typedef struct cuboid_server cuboid_server;
+
+typedef struct cuboid_server_config {
+    uint32_t streams;             /* launches in flight at once (0 = 2)                  */
+    uint32_t max_slots;           /* requests admitted at once (0 = 4096)                */
+    uint64_t max_launch_units;    /* units per launch (0 = 2^20)                         */
+    uint64_t hbm_budget_bytes;    /* device memory for per-request row orders (0 = 1 GiB) */
+} cuboid_server_config;
+
+typedef struct cuboid_server_stats {
+    uint64_t submitted, completed, launches, units;
+    uint32_t max_admitted;        /* most requests admitted at the same time */
+    uint32_t reserved;
+} cuboid_server_stats;
+
+typedef struct cuboid_request_timing {
+    uint64_t submit_ns, admit_ns, done_ns;   /* steady clock, nanoseconds */
+} cuboid_request_timing;
+
+/*
+ * Start a server.  primes as in cuboid_sieve_range.  cfg may be NULL.
+ * While a server runs, cuboid_destroy on its context returns E_BUSY.
+ * Errors: E_PRIMES, E_ARG, E_DEVICE, E_NOT_LOADED.
+ */
+int cuboid_server_start(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes,
+                        const cuboid_server_config *cfg, cuboid_server **out);
+
+/*
+ * Queue one rectangle; *ticket identifies it.  Returns at once.
+ * Errors: E_RANGE (invalid rectangle), E_LIMIT (p1 >= 2^24), E_BUSY (stopping).
+ */
+int cuboid_server_submit(cuboid_server *srv, const cuboid_request *req, uint64_t *ticket);
+
+/*
+ * Results of a ticket into res (counts[n_primes], survivors up to res->cap,
+ * n_survivors, n_pairs, status).  wait = 0 returns E_BUSY when not finished;
+ * wait != 0 blocks until it is.  A ticket's results are handed out once:
+ * after a successful poll the ticket is forgotten.  E_CAPACITY leaves the
+ * results in place (n_survivors set) so the caller can poll again with room.
+ * timing may be NULL.  Errors: E_ARG (unknown ticket), E_BUSY, E_CAPACITY.
+ */
+int cuboid_server_poll(cuboid_server *srv, uint64_t ticket, cuboid_result *res, int wait,
+                       cuboid_request_timing *timing);
+
+int cuboid_server_stats_get(cuboid_server *srv, cuboid_server_stats *out);
+
+/* Finish every admitted and pending request, stop the worker, free the server. */
+int cuboid_server_stop(cuboid_server *srv);
 
 /* ------------------------------------------------------------------ tuning */
 

@@ -42,13 +42,17 @@ class cuboid_timing(ctypes.Structure):
 
 
 class cuboid_server_config(ctypes.Structure):
-    _fields_ = [("streams", u32), ("max_inflight_units", u64), ("hbm_budget_bytes", u64),
-                ("max_batch_requests", u32), ("reserved", u32)]
+    _fields_ = [("streams", u32), ("max_slots", u32), ("max_launch_units", u64),
+                ("hbm_budget_bytes", u64)]
 
 
 class cuboid_server_stats(ctypes.Structure):
     _fields_ = [("submitted", u64), ("completed", u64), ("launches", u64), ("units", u64),
-                ("max_concurrent_requests", u32), ("reserved", u32)]
+                ("max_admitted", u32), ("reserved", u32)]
+
+
+class cuboid_request_timing(ctypes.Structure):
+    _fields_ = [("submit_ns", u64), ("admit_ns", u64), ("done_ns", u64)]
 
 
 class CuboidError(RuntimeError):
@@ -91,8 +95,8 @@ def _load():
         "cuboid_last_timing": ([vp, P(cuboid_timing)], i32),
         "cuboid_server_start": ([vp, P(u32), u32, P(cuboid_server_config), P(vp)], i32),
         "cuboid_server_submit": ([vp, P(cuboid_request), P(u64)], i32),
-        "cuboid_server_poll": ([vp, u64, P(cuboid_result), i32], i32),
-        "cuboid_server_stats": ([vp, P(cuboid_server_stats)], i32),
+        "cuboid_server_poll": ([vp, u64, P(cuboid_result), i32, P(cuboid_request_timing)], i32),
+        "cuboid_server_stats_get": ([vp, P(cuboid_server_stats)], i32),
         "cuboid_server_stop": ([vp], i32),
     }
     for name, (args, res) in sigs.items():
@@ -317,6 +321,59 @@ def cuboid_autotune(ctx, primes, cache_path=None):
     _check(_load().cuboid_autotune(ctx, _p(pr, u32), len(pr), cp, ctypes.byref(t)),
            "cuboid_autotune")
     return dict(dense_primes=t.dense_primes, workgroups=t.workgroups, lds_budget=t.lds_budget)
+
+
+def cuboid_server_start(ctx, primes, streams=0, max_slots=0, max_launch_units=0,
+                        hbm_budget_bytes=0):
+    pr = _arr(primes, np.uint32)
+    cfg = cuboid_server_config(int(streams), int(max_slots), int(max_launch_units),
+                               int(hbm_budget_bytes))
+    h = ctypes.c_void_p()
+    _check(_load().cuboid_server_start(ctx, _p(pr, u32), len(pr), ctypes.byref(cfg),
+                                       ctypes.byref(h)), "cuboid_server_start")
+    return h
+
+
+def cuboid_server_submit(srv, rect):
+    r = cuboid_request(*[int(x) for x in rect])
+    t = ctypes.c_uint64(0)
+    _check(_load().cuboid_server_submit(srv, ctypes.byref(r), ctypes.byref(t)),
+           "cuboid_server_submit")
+    return t.value
+
+
+def cuboid_server_poll(srv, ticket, n_primes, cap=1024, wait=True):
+    """dict(status, counts, n_pairs, n_survivors, survivors, latency_ns, ...) or
+    None when wait is False and the ticket is not finished."""
+    counts = np.zeros(max(1, n_primes), dtype=np.uint64)
+    surv = np.zeros(max(1, cap), dtype=np.uint64)
+    res = cuboid_result()
+    res.survivors = _p(surv, u64)
+    res.cap = int(cap)
+    res.counts = _p(counts, u64)
+    tim = cuboid_request_timing()
+    st = _load().cuboid_server_poll(srv, int(ticket), ctypes.byref(res), 1 if wait else 0,
+                                    ctypes.byref(tim))
+    if st == E_BUSY and not wait:
+        return None
+    if st not in (OK,):
+        raise CuboidError(st, "cuboid_server_poll",
+                          needed=res.n_survivors if st == E_CAPACITY else None)
+    return dict(status=res.status, counts=counts[:n_primes], n_pairs=res.n_pairs,
+                n_survivors=res.n_survivors, survivors=surv[:res.n_survivors].copy(),
+                submit_ns=tim.submit_ns, admit_ns=tim.admit_ns, done_ns=tim.done_ns,
+                latency_ns=tim.done_ns - tim.submit_ns)
+
+
+def cuboid_server_stats_get(srv):
+    st = cuboid_server_stats()
+    _check(_load().cuboid_server_stats_get(srv, ctypes.byref(st)), "cuboid_server_stats_get")
+    return dict(submitted=st.submitted, completed=st.completed, launches=st.launches,
+                units=st.units, max_admitted=st.max_admitted)
+
+
+def cuboid_server_stop(srv):
+    _check(_load().cuboid_server_stop(srv), "cuboid_server_stop")
 
 
 class Context:

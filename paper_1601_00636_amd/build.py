@@ -21,10 +21,13 @@ SOURCES = [
     "bigint.cpp",
     "context.cpp",
     "autotune.cpp",
+    "server.cpp",
     "api.cpp",
 ]
 
-HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+HIPCC = os.environ.get("HIPCC", ROCM + "/bin/hipcc")
+CXX = os.environ.get("CXX", "g++")
 ARCH = "gfx950"
 # packed FP32 instructions stay off (no float arithmetic on the hot path anyway)
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
@@ -38,7 +41,9 @@ def _compile(src):
     if src.endswith(".hip"):
         cmd = [HIPCC] + DEVICE + COMMON + ["-x", "hip", "-c", path, "-o", obj]
     else:
-        cmd = [HIPCC] + COMMON + ["-D__HIP_PLATFORM_AMD__", "-c", path, "-o", obj]
+        # host-only C++ (HIP runtime API through its headers)
+        cmd = [CXX] + COMMON + ["-D__HIP_PLATFORM_AMD__", "-I" + ROCM + "/include", "-pthread",
+                                "-c", path, "-o", obj]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s" % (" ".join(cmd), r.stdout))

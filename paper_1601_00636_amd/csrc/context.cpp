@@ -239,9 +239,13 @@ int build_dense(cuboid_ctx *ctx, Plan *pl, uint32_t K, DenseSet **out) {
 }
 
 // Resident row table for 1 <= p <= R, grown to cover p_max when p_max <= 2^24.
-int ensure_rows(cuboid_ctx *ctx, uint32_t p_max) {
+// Growing reallocates the table, so it is refused (E_BUSY) while a server may
+// have launches reading it, except from the one server when it is drained.
+static int ensure_rows_impl(cuboid_ctx *ctx, uint32_t p_max, bool from_server) {
     if (p_max <= ctx->rows_R) return CUBOID_OK;
     if (p_max > kResidentRowsMax) return CUBOID_E_LIMIT;
+    const int servers = ctx->servers.load();
+    if (servers > (from_server ? 1 : 0)) return CUBOID_E_BUSY;
     uint64_t R = 1u << 16;
     while (R < p_max) R <<= 1;
     if (R > kResidentRowsMax) R = kResidentRowsMax;
@@ -253,6 +257,12 @@ int ensure_rows(cuboid_ctx *ctx, uint32_t p_max) {
     HIPCHK(hipStreamSynchronize(ctx->stream));
     ctx->rows_R = (uint32_t)R;
     return CUBOID_OK;
+}
+
+int ensure_rows(cuboid_ctx *ctx, uint32_t p_max) { return ensure_rows_impl(ctx, p_max, false); }
+
+int ensure_rows_serving(cuboid_ctx *ctx, uint32_t p_max) {
+    return ensure_rows_impl(ctx, p_max, true);
 }
 
 cuboid_tuning tuning_for(cuboid_ctx *ctx, const std::vector<uint32_t> &primes, const Plan &pl) {
@@ -284,7 +294,10 @@ int launch_reqs(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboi
         r.nrb = (uint32_t)((rows + 63) / 64);
         r.nwin = (uint32_t)(((uint64_t)r.q1 - r.q0 + 64) / 64);
         r.unit0 = units;
-        units += (uint64_t)r.nrb * r.nwin;
+        r.ulo = 0;
+        r.ucount = (uint64_t)r.nrb * r.nwin;
+        r.slot = slot0 + i;
+        units += r.ucount;
         const bool group = ctx->bucketing && rows >= kBucketMinRows &&
                            row_prefix[i] + rows <= kMaxOrderRows;
         row_prefix[i + 1] = row_prefix[i] + (group ? rows : 0);
@@ -336,10 +349,9 @@ int launch_reqs(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboi
     P.ipool = (const uint16_t *)pl.ipool.p;
     P.req = (const ReqDesc *)ctx->reqbuf.p;
     P.n_req = n;
-    P.req_base = slot0;
     P.n_units = units;
-    P.counts = (unsigned long long *)ctx->counts.p + (uint64_t)slot0 * P.nc;
-    P.pairs = (unsigned long long *)ctx->pairs.p + slot0;
+    P.counts = (unsigned long long *)ctx->counts.p;
+    P.pairs = (unsigned long long *)ctx->pairs.p;
     P.n_rep = ctx->n_rep;
     P.rep_stride_counts = ctx->rep_stride_counts;
     P.rep_stride_pairs = ctx->rep_stride_pairs;

@@ -48,6 +48,10 @@ struct ReqDesc {
     uint32_t nrb;          // ceil(rows / 64)
     uint32_t nwin;         // ceil(cols / 64)
     uint64_t unit0;        // first unit of this request in the flattened order
+    uint64_t ulo;          // this launch covers the request's units ulo .. ulo + ucount - 1
+    uint64_t ucount;       //   (unit rb * nwin + win: row block rb, column window win)
+    uint32_t slot;         // counter slot and survivor tag of the request
+    uint32_t pad;
     const RowInfo *rows;   // row info for p at rows[p - rows_p0]
     uint32_t rows_p0;
     uint32_t ip0;          // p0 of the caller's rectangle (survivor indices)
@@ -57,7 +61,7 @@ struct ReqDesc {
 
 struct SurvEntry {
     uint64_t idx;          // (p - p0) * (q1 - q0 + 1) + (q - q0)
-    uint32_t req;          // request number within the launch
+    uint32_t req;          // slot of the request
     uint32_t pad;
 };
 
@@ -78,10 +82,10 @@ struct SweepParams {
     const uint16_t *ipool;               // inverse tables
     const ReqDesc *req;
     uint32_t n_req;
-    uint32_t req_base;                   // added to request numbers in survivor entries
+    uint32_t pad0;
     uint64_t n_units;
-    unsigned long long *counts;          // [n_rep][..][nc], canonical ascending order
-    unsigned long long *pairs;           // [n_rep][..]
+    unsigned long long *counts;          // [n_rep][slot][nc], canonical ascending order
+    unsigned long long *pairs;           // [n_rep][slot]
     uint32_t n_rep;                      // counter replicas (power of two), by wave
     uint32_t pad1;
     uint64_t rep_stride_counts;          // elements between replicas
@@ -128,6 +132,14 @@ hipError_t launch_row_info(const uint32_t *primes16, const uint32_t *magic16, ui
 hipError_t launch_bucket_rows(const ReqDesc *req, uint32_t n_req, const uint64_t *chunk_prefix,
                               uint64_t n_chunks, const uint64_t *row_prefix, uint32_t *order,
                               hipStream_t s);
+// zero all replicas of the listed counter slots; sum them into out[i][nc + 1]
+hipError_t launch_zero_slots(unsigned long long *counts, unsigned long long *pairs,
+                             const uint32_t *slots, uint32_t n, uint32_t nc, uint32_t n_rep,
+                             uint64_t stride_c, uint64_t stride_p, hipStream_t s);
+hipError_t launch_reduce_slots(const unsigned long long *counts, const unsigned long long *pairs,
+                               const uint32_t *slots, uint32_t n, uint32_t nc, uint32_t n_rep,
+                               uint64_t stride_c, uint64_t stride_p, unsigned long long *out,
+                               hipStream_t s);
 // dst[i] = sum of n_rep replicas src[r * stride + i], in place on replica 0
 hipError_t launch_reduce_replicas(unsigned long long *buf, uint64_t n, uint32_t n_rep,
                                   uint64_t stride, hipStream_t s);

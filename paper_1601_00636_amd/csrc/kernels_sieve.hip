@@ -64,7 +64,7 @@ __constant__ uint16_t c_pat_off[64] = {
 
 // Tests the pairs of one queued window against the deep primes, in ascending
 // order; counts the first rejecting prime, appends unrejected pairs.
-__device__ __forceinline__ void deep_window(const SweepParams &P, const QEntry e, uint32_t ri,
+__device__ __forceinline__ void deep_window(const SweepParams &P, const QEntry e,
                                             const ReqDesc &R, uint32_t *dcnt,
                                             unsigned long long *cnt_rep) {
     uint64_t mask = e.mask;
@@ -83,7 +83,7 @@ __device__ __forceinline__ void deep_window(const SweepParams &P, const QEntry e
                 if (i < kDeepCounters)
                     atomicAdd(&dcnt[i], 1u);
                 else
-                    atomicAdd(&cnt_rep[(uint64_t)ri * P.nc + P.K + i], 1ull);
+                    atomicAdd(&cnt_rep[(uint64_t)R.slot * P.nc + P.K + i], 1ull);
                 rejected = true;
                 break;
             }
@@ -93,7 +93,7 @@ __device__ __forceinline__ void deep_window(const SweepParams &P, const QEntry e
             if (pos < P.surv_cap) {
                 SurvEntry s;
                 s.idx = (uint64_t)(e.p - R.ip0) * width + (q - R.q0);
-                s.req = ri + P.req_base;
+                s.req = R.slot;
                 s.pad = 0;
                 P.surv[pos] = s;
             }
@@ -157,14 +157,14 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
 
     auto drain = [&](uint32_t n, const ReqDesc &R) {
         __builtin_amdgcn_wave_barrier();
-        if (lane < n) deep_window(P, queue[qn - n + lane], ri, R, dcnt, cnt_rep);
+        if (lane < n) deep_window(P, queue[qn - n + lane], R, dcnt, cnt_rep);
         __builtin_amdgcn_wave_barrier();
         qn = uni(qn - n);
     };
 
     auto flush = [&](const ReqDesc &R) {
         while (qn) drain(qn < (uint32_t)kWave ? qn : (uint32_t)kWave, R);
-        const uint64_t cbase = (uint64_t)ri * P.nc;
+        const uint64_t cbase = (uint64_t)R.slot * P.nc;
 #pragma unroll
         for (int k = 0; k < KD; ++k) {
             const uint32_t s = wave_sum(cnt[k]);
@@ -172,7 +172,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
             cnt[k] = 0;
         }
         const uint32_t s = wave_sum(npairs);
-        if (lane == 0 && s) atomicAdd(&pairs_rep[ri], (unsigned long long)s);
+        if (lane == 0 && s) atomicAdd(&pairs_rep[R.slot], (unsigned long long)s);
         npairs = 0;
         __builtin_amdgcn_wave_barrier();
         const uint32_t ndc = P.n_deep < kDeepCounters ? P.n_deep : kDeepCounters;
@@ -192,16 +192,18 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
         R.p0 = uni(R.p0); R.p1 = uni(R.p1); R.q0 = uni(R.q0); R.q1 = uni(R.q1);
         R.nrb = uni(R.nrb); R.nwin = uni(R.nwin); R.unit0 = uni64(R.unit0);
         R.rows_p0 = uni(R.rows_p0); R.ip0 = uni(R.ip0);
-        const uint64_t rend = R.unit0 + (uint64_t)R.nrb * R.nwin;
+        R.ulo = uni64(R.ulo); R.ucount = uni64(R.ucount); R.slot = uni(R.slot);
+        const uint64_t rend = R.unit0 + R.ucount;
         if (u >= rend) {
             flush(R);
             ri = uni(ri + 1);
             continue;
         }
-        const uint64_t local = u - R.unit0;
+        const uint64_t local = u - R.unit0 + R.ulo;
         const uint32_t rb = uni((uint32_t)(local / R.nwin));
         const uint32_t win0 = uni((uint32_t)(local % R.nwin));
-        uint64_t seg_end = R.unit0 + (uint64_t)(rb + 1) * R.nwin;
+        uint64_t seg_end = R.unit0 + ((uint64_t)(rb + 1) * R.nwin - R.ulo);
+        if (seg_end > rend) seg_end = rend;
         if (seg_end > uend) seg_end = uend;
         uint32_t nw = uni((uint32_t)(seg_end - u));
         if (nw > kFlushWindows - since_flush) nw = uni(kFlushWindows - since_flush);
@@ -216,8 +218,14 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
         for (int f = 0; f < kMaxBigFactors; ++f) rinfo.f[f] = 0;
         if (valid) {
             p = R.order ? R.order[ridx] : R.p0 + (uint32_t)ridx;
-            rinfo = R.rows[p - R.rows_p0];
-            rinfo.meta &= ~8u;
+            // a row order holds only rows of this request; anything else
+            // leaves the lane idle rather than indexing outside the row table
+            if (p < R.p0 || p > R.p1) {
+                p = 0;
+            } else {
+                rinfo = R.rows[p - R.rows_p0];
+                rinfo.meta &= ~8u;
+            }
         }
         const uint32_t nf = (rinfo.meta >> 4) & 15;
         const uint32_t nfmax = uni(wave_max(nf));

@@ -261,6 +261,36 @@ __global__ void __launch_bounds__(256) bucket_rows_kernel(const ReqDesc *req, ui
     }
 }
 
+// Counter slots of a request: zero every replica of each listed slot.
+__global__ void zero_slots_kernel(unsigned long long *counts, unsigned long long *pairs,
+                                  const uint32_t *slots, uint32_t n, uint32_t nc, uint32_t n_rep,
+                                  uint64_t stride_c, uint64_t stride_p) {
+    const uint64_t per = (uint64_t)(nc + 1) * n_rep;
+    for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < per * n;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t i = (uint32_t)(g / per), e = (uint32_t)(g % per);
+        const uint32_t r = e / (nc + 1), k = e % (nc + 1);
+        if (k < nc) counts[r * stride_c + (uint64_t)slots[i] * nc + k] = 0;
+        else pairs[r * stride_p + slots[i]] = 0;
+    }
+}
+
+// Sum the replicas of each listed slot into out[i * (nc + 1) + k] (k = nc: pairs).
+__global__ void reduce_slots_kernel(const unsigned long long *counts,
+                                    const unsigned long long *pairs, const uint32_t *slots,
+                                    uint32_t n, uint32_t nc, uint32_t n_rep, uint64_t stride_c,
+                                    uint64_t stride_p, unsigned long long *out) {
+    for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < (uint64_t)n * (nc + 1);
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t i = (uint32_t)(g / (nc + 1)), k = (uint32_t)(g % (nc + 1));
+        unsigned long long acc = 0;
+        for (uint32_t r = 0; r < n_rep; ++r)
+            acc += k < nc ? counts[r * stride_c + (uint64_t)slots[i] * nc + k]
+                          : pairs[r * stride_p + slots[i]];
+        out[g] = acc;
+    }
+}
+
 __global__ void reduce_replicas_kernel(unsigned long long *buf, uint64_t n, uint32_t n_rep,
                                        uint64_t stride) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
@@ -372,6 +402,27 @@ hipError_t launch_bucket_rows(const ReqDesc *req, uint32_t n_req, const uint64_t
     if (!n_chunks) return hipSuccess;
     hipLaunchKernelGGL(bucket_rows_kernel, dim3((unsigned)n_chunks), dim3(256), 0, s, req, n_req,
                        chunk_prefix, row_prefix, order);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_slots(unsigned long long *counts, unsigned long long *pairs,
+                             const uint32_t *slots, uint32_t n, uint32_t nc, uint32_t n_rep,
+                             uint64_t stride_c, uint64_t stride_p, hipStream_t s) {
+    if (!n) return hipSuccess;
+    const uint64_t work = (uint64_t)n * (nc + 1) * n_rep;
+    hipLaunchKernelGGL(zero_slots_kernel, dim3(grid_for(work)), dim3(kBlock), 0, s, counts, pairs,
+                       slots, n, nc, n_rep, stride_c, stride_p);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_slots(const unsigned long long *counts, const unsigned long long *pairs,
+                               const uint32_t *slots, uint32_t n, uint32_t nc, uint32_t n_rep,
+                               uint64_t stride_c, uint64_t stride_p, unsigned long long *out,
+                               hipStream_t s) {
+    if (!n) return hipSuccess;
+    const uint64_t work = (uint64_t)n * (nc + 1);
+    hipLaunchKernelGGL(reduce_slots_kernel, dim3(grid_for(work)), dim3(kBlock), 0, s, counts, pairs,
+                       slots, n, nc, n_rep, stride_c, stride_p, out);
     return hipGetLastError();
 }
 

@@ -119,6 +119,8 @@ int build_plan(cuboid_ctx *ctx, const std::vector<uint32_t> &primes, Plan **out)
 uint32_t default_dense(const Plan &pl, uint32_t lds_budget);
 int build_dense(cuboid_ctx *ctx, Plan *pl, uint32_t K, DenseSet **out);
 int ensure_rows(cuboid_ctx *ctx, uint32_t p_max);
+int ensure_rows_serving(cuboid_ctx *ctx, uint32_t p_max);   // by a drained server
+std::vector<int32_t> count_columns(const Plan &pl, const std::vector<uint32_t> &caller);
 cuboid_tuning tuning_for(cuboid_ctx *ctx, const std::vector<uint32_t> &primes, const Plan &pl);
 int rect_valid(uint32_t p0, uint32_t p1, uint32_t q0, uint32_t q1);
 // Results of one sieve call over several rectangles.
