@@ -62,6 +62,23 @@ def mean_depth(counts_total, n_surv, primes, trivial):
     return tot, k
 
 
+def measured_traffic():
+    """HBM traffic of the sweep from the committed rocprofv3 counter summary,
+    only while the sweep kernel's source is the one the counters were taken on."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    try:
+        with open(os.path.join(here, "profiles", "sweep_traffic.json")) as f:
+            rec = json.load(f)
+        with open(os.path.join(here, "paper_1601_00636_amd", "csrc", "kernels_sieve.hip"), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None, None
+    if rec.get("kernel_source_sha256") != sha:
+        return None, None
+    return rec["traffic_GBps"], rec["traffic_bytes_per_launch"]
+
+
 def run_cpu_baseline(reqs, primes, stride):
     import oracle
     for r in primes:
@@ -76,6 +93,23 @@ def run_cpu_baseline(reqs, primes, stride):
     return dict(value=pairs / dt, unit="coprime pairs/s", cores=threads, kind="oracle",
                 sample="every %dth of the 4096 batched rectangles (%d rectangles, %d coprime "
                        "pairs) in %.1f s; tables excluded" % (stride, len(sample), pairs, dt))
+
+
+def calibrate_copy():
+    """A plain copy of 2^28 float32 (1 GiB read, 1 GiB written), five times: the
+    reference the HBM byte counters of the sweep are scaled by."""
+    import torch
+    x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 5
+    print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30,
+                      "seconds": dt, "GBps_read_plus_write": 2 * (1 << 30) / dt / 1e9}))
+    return 0
 
 
 def run_served(cb, wl, ctx, primes, seconds):
@@ -113,7 +147,11 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=64)
     ap.add_argument("--served-seconds", type=float, default=10.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        return calibrate_copy()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus %d is not supported "
@@ -176,6 +214,7 @@ def main():
     wbar = omega_weighted(reqs)
     ops_pair = 4 * dbar + 3 * wbar + 1
     achieved = ops_pair * n_pairs / (sweep_avg * 1e-3)
+    traffic_gbps, traffic_bytes = measured_traffic()
 
     res = {
         "metric": METRIC,
@@ -197,7 +236,9 @@ def main():
                    "tuning": tun},
         "extras": {},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT32_PEAK / 1e12,
-                     "unit": "Tops/s (INT32)", "frac": achieved / INT32_PEAK, "traffic": None,
+                     "unit": "Tops/s (INT32)", "frac": achieved / INT32_PEAK, "traffic": traffic_gbps,
+                     "traffic_unit": "GB/s HBM (FETCH_SIZE, WRITE_SIZE scaled by a 1 GiB copy)",
+                     "traffic_bytes_per_launch": traffic_bytes,
                      "kernel": "sweep_kernel", "sweep_ms": sweep_avg,
                      "ops_per_pair": ops_pair, "mean_lookups": dbar, "mean_omega": wbar,
                      "units_64x64": tim["units"]},
