@@ -149,9 +149,9 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
         ri = uni(lo);
     }
 
-    uint32_t cnt[KD + 1];
-    for (int k = 0; k <= KD; ++k) cnt[k] = 0;
-    uint32_t npairs = 0;
+    uint32_t left[KD + 1], left_hi[KD + 1];
+    for (int k = 0; k <= KD; ++k) { left[k] = 0; left_hi[k] = 0; }
+    uint32_t npairs = 0, npairs_hi = 0;
     uint32_t qn = 0;            // queued windows (wave-uniform)
     uint32_t since_flush = 0;   // windows since counters were flushed (wave-uniform)
 
@@ -165,15 +165,20 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
     auto flush = [&](const ReqDesc &R) {
         while (qn) drain(qn < (uint32_t)kWave ? qn : (uint32_t)kWave, R);
         const uint64_t cbase = (uint64_t)R.slot * P.nc;
+        uint32_t before = npairs + npairs_hi;
 #pragma unroll
         for (int k = 0; k < KD; ++k) {
-            const uint32_t s = wave_sum(cnt[k]);
+            const uint32_t now = left[k] + left_hi[k];
+            const uint32_t s = wave_sum(before - now);
             if (lane == 0 && s) atomicAdd(&cnt_rep[cbase + k], (unsigned long long)s);
-            cnt[k] = 0;
+            before = now;
+            left[k] = 0;
+            left_hi[k] = 0;
         }
-        const uint32_t s = wave_sum(npairs);
+        const uint32_t s = wave_sum(npairs + npairs_hi);
         if (lane == 0 && s) atomicAdd(&pairs_rep[R.slot], (unsigned long long)s);
         npairs = 0;
+        npairs_hi = 0;
         __builtin_amdgcn_wave_barrier();
         const uint32_t ndc = P.n_deep < kDeepCounters ? P.n_deep : kDeepCounters;
         for (uint32_t i = lane; i < ndc; i += kWave) {
@@ -279,14 +284,12 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
                 if (p == 1) alive &= ~1ull;   // (1, 1) is coprime but p = q
             }
             npairs = __builtin_popcount((uint32_t)alive) + npairs;
-            npairs = __builtin_popcount((uint32_t)(alive >> 32)) + npairs;
+            npairs_hi = __builtin_popcount((uint32_t)(alive >> 32)) + npairs_hi;
 #pragma unroll
             for (int d = 0; d < KD; ++d) {
-                const uint64_t win = lds64(smem, lb[d] + ok[d] * 8);
-                const uint64_t hit = alive & win;
-                cnt[d] = __builtin_popcount((uint32_t)hit) + cnt[d];
-                cnt[d] = __builtin_popcount((uint32_t)(hit >> 32)) + cnt[d];
-                alive ^= hit;
+                alive &= ~lds64(smem, lb[d] + ok[d] * 8);
+                left[d] = __builtin_popcount((uint32_t)alive) + left[d];
+                left_hi[d] = __builtin_popcount((uint32_t)(alive >> 32)) + left_hi[d];
                 ok[d] += P.dstep[d];
                 if (ok[d] >= P.dr[d]) ok[d] -= P.dr[d];
             }
