@@ -244,8 +244,22 @@ def main():
                      "units_64x64": tim["units"]},
     }
 
+    res["config"]["launch"] = {0: "call by call", 1: "hip graph replay",
+                               2: "hip graph captured"}[tim["graph"]]
     if not args.no_extras:
         extras = res["extras"]
+        # the same batch launched call by call instead of as one graph replay
+        cb.cuboid_enable_graphs(ctx, False)
+        step()
+        torch.cuda.synchronize()
+        n_eager = max(3, args.steps // 2)
+        t0 = time.perf_counter()
+        for _ in range(n_eager):
+            step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / n_eager
+        cb.cuboid_enable_graphs(ctx, True)
+        extras["batched_call_by_call"] = {"value": n_pairs / dt, "ms_per_step": dt * 1e3}
         # the same 4096 rectangles as separate plain launches
         t0 = time.perf_counter()
         tot = 0

@@ -302,10 +302,20 @@ typedef struct cuboid_timing {
     uint64_t units;          /* 64 x 64 work units the sweep processed          */
     uint32_t dense_primes;   /* K used                                          */
     uint32_t workgroups;     /* grid used                                       */
+    uint32_t graph;          /* 0 launched call by call, 1 replayed a captured  */
+                             /* graph, 2 captured a new graph and launched it   */
+    uint32_t reserved;
 } cuboid_timing;
 
 /* Turn per-call HIP-event timing on (1) or off (0). */
 int cuboid_enable_timing(cuboid_ctx *ctx, int on);
+/* Batched and plain sieve calls over rows below 2^24 run as one replay of a
+ * captured HIP graph (1, the default) or as separate launches (0).  Either
+ * way the results are the same.  A graph is captured on first use of a
+ * request count, prime list, tuning and buffer set, and replayed for later
+ * calls that share them; up to 8 graphs are kept per context.  Turning graphs
+ * off frees them.  E_DEVICE if capture fails. */
+int cuboid_enable_graphs(cuboid_ctx *ctx, int on);
 /* Timing of the last sieve call on this context. */
 int cuboid_last_timing(cuboid_ctx *ctx, cuboid_timing *out);
 

@@ -38,7 +38,7 @@ class cuboid_tuning(ctypes.Structure):
 
 class cuboid_timing(ctypes.Structure):
     _fields_ = [("sweep_ms", ctypes.c_double), ("total_gpu_ms", ctypes.c_double), ("units", u64),
-                ("dense_primes", u32), ("workgroups", u32)]
+                ("dense_primes", u32), ("workgroups", u32), ("graph", u32), ("reserved", u32)]
 
 
 class cuboid_server_config(ctypes.Structure):
@@ -93,6 +93,7 @@ def _load():
         "cuboid_get_tuning": ([vp, P(u32), u32, P(cuboid_tuning)], i32),
         "cuboid_enable_timing": ([vp, i32], i32),
         "cuboid_last_timing": ([vp, P(cuboid_timing)], i32),
+        "cuboid_enable_graphs": ([vp, i32], i32),
         "cuboid_server_start": ([vp, P(u32), u32, P(cuboid_server_config), P(vp)], i32),
         "cuboid_server_submit": ([vp, P(cuboid_request), P(u64)], i32),
         "cuboid_server_poll": ([vp, u64, P(cuboid_result), i32, P(cuboid_request_timing)], i32),
@@ -292,7 +293,11 @@ def cuboid_last_timing(ctx):
     t = cuboid_timing()
     _check(_load().cuboid_last_timing(ctx, ctypes.byref(t)), "cuboid_last_timing")
     return dict(sweep_ms=t.sweep_ms, total_gpu_ms=t.total_gpu_ms, units=t.units,
-                dense_primes=t.dense_primes, workgroups=t.workgroups)
+                dense_primes=t.dense_primes, workgroups=t.workgroups, graph=t.graph)
+
+
+def cuboid_enable_graphs(ctx, on=True):
+    _check(_load().cuboid_enable_graphs(ctx, 1 if on else 0), "cuboid_enable_graphs")
 
 
 def cuboid_set_tuning(ctx, primes, dense_primes=None, workgroups=0, lds_budget=0):

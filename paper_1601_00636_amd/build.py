@@ -19,6 +19,7 @@ SOURCES = [
     "kernels_sieve.hip",
     "kernels_roots.hip",
     "bigint.cpp",
+    "graph.cpp",
     "context.cpp",
     "autotune.cpp",
     "server.cpp",

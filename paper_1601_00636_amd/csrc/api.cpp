@@ -88,6 +88,7 @@ int init_ctx(cuboid_ctx *ctx, int dev) {
 void free_ctx(cuboid_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    drop_graphs(ctx);
     if (ctx->ev_sweep0) (void)hipEventDestroy(ctx->ev_sweep0);
     if (ctx->ev_sweep1) (void)hipEventDestroy(ctx->ev_sweep1);
     if (ctx->ev_total0) (void)hipEventDestroy(ctx->ev_total0);
@@ -389,6 +390,15 @@ int cuboid_enable_timing(cuboid_ctx *ctx, int on) {
     if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
     std::lock_guard<std::recursive_mutex> g(ctx->mu);
     ctx->timing = on != 0;
+    return CUBOID_OK;
+}
+
+int cuboid_enable_graphs(cuboid_ctx *ctx, int on) {
+    if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
+    std::lock_guard<std::recursive_mutex> g(ctx->mu);
+    if (set_device(ctx)) return CUBOID_E_DEVICE;
+    ctx->use_graphs = on != 0;
+    if (!ctx->use_graphs) drop_graphs(ctx);
     return CUBOID_OK;
 }
 

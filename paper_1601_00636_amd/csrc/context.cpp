@@ -277,17 +277,15 @@ cuboid_tuning tuning_for(cuboid_ctx *ctx, const std::vector<uint32_t> &primes, c
     return t;
 }
 
-// One sweep launch over `reqs` (already holding row pointers), accumulating
-// into the context's count / pair / survivor buffers (zeroed by the caller).
-// Request j of this launch uses counter slot slot0 + j and survivor request
-// number slot0 + j.
-int launch_reqs(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid_tuning &tun,
-                std::vector<ReqDesc> &reqs, uint32_t slot0, uint64_t surv_cap, hipStream_t s,
-                uint64_t *units_out) {
+// Unit space of one launch: each request's first unit, unit count and counter
+// slot (slot0 + its position), and which requests get their rows regrouped by
+// factor count (prefix sums of regrouped rows and of 8192-row chunks).
+void shape_reqs(cuboid_ctx *ctx, std::vector<ReqDesc> &reqs, uint32_t slot0, LaunchShape *sh) {
     const uint32_t n = (uint32_t)reqs.size();
+    sh->row_prefix.assign(n + 1, 0);
+    sh->chunk_prefix.assign(n + 1, 0);
     uint64_t units = 0;
-    // requests with enough rows get their rows regrouped by factor count
-    std::vector<uint64_t> row_prefix(n + 1, 0), chunk_prefix(n + 1, 0);
+    uint32_t max_p = 0;
     for (uint32_t i = 0; i < n; ++i) {
         ReqDesc &r = reqs[i];
         const uint64_t rows = (uint64_t)r.p1 - r.p0 + 1;
@@ -298,40 +296,27 @@ int launch_reqs(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboi
         r.ucount = (uint64_t)r.nrb * r.nwin;
         r.slot = slot0 + i;
         units += r.ucount;
+        max_p = std::max(max_p, r.p1);
         const bool group = ctx->bucketing && rows >= kBucketMinRows &&
-                           row_prefix[i] + rows <= kMaxOrderRows;
-        row_prefix[i + 1] = row_prefix[i] + (group ? rows : 0);
-        chunk_prefix[i + 1] = chunk_prefix[i] + (group ? (rows + kBucketChunk - 1) / kBucketChunk : 0);
+                           sh->row_prefix[i] + rows <= kMaxOrderRows;
+        sh->row_prefix[i + 1] = sh->row_prefix[i] + (group ? rows : 0);
+        sh->chunk_prefix[i + 1] =
+            sh->chunk_prefix[i] + (group ? (rows + kBucketChunk - 1) / kBucketChunk : 0);
     }
-    const uint64_t n_order = row_prefix[n], n_chunks = chunk_prefix[n];
-    if (n_order) {
-        HIPCHK(ctx->order.ensure(n_order * 4));
-        for (uint32_t i = 0; i < n; ++i)
-            reqs[i].order = row_prefix[i + 1] > row_prefix[i]
-                                ? (const uint32_t *)ctx->order.p + row_prefix[i] : nullptr;
-    } else {
-        for (auto &r : reqs) r.order = nullptr;
-    }
-    // staged through pinned memory; the previous user of the staging buffer
-    // on this stream has completed once the stream is idle
-    HIPCHK(hipStreamSynchronize(s));
-    HIPCHK(ctx->req_stage.ensure(n * sizeof(ReqDesc) + 2 * (n + 1) * 8));
-    unsigned char *stage = (unsigned char *)ctx->req_stage.p;
-    memcpy(stage, reqs.data(), n * sizeof(ReqDesc));
-    HIPCHK(ctx->reqbuf.ensure(n * sizeof(ReqDesc)));
-    HIPCHK(hipMemcpyAsync(ctx->reqbuf.p, stage, n * sizeof(ReqDesc), hipMemcpyHostToDevice, s));
-    if (n_order) {
-        uint64_t *pre = (uint64_t *)(stage + n * sizeof(ReqDesc));
-        memcpy(pre, chunk_prefix.data(), (n + 1) * 8);
-        memcpy(pre + n + 1, row_prefix.data(), (n + 1) * 8);
-        HIPCHK(ctx->chunk_prefix.ensure((n + 1) * 8));
-        HIPCHK(ctx->row_prefix.ensure((n + 1) * 8));
-        HIPCHK(hipMemcpyAsync(ctx->chunk_prefix.p, pre, (n + 1) * 8, hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(ctx->row_prefix.p, pre + n + 1, (n + 1) * 8, hipMemcpyHostToDevice, s));
-        HIPCHK(launch_bucket_rows((const ReqDesc *)ctx->reqbuf.p, n,
-                                  (const uint64_t *)ctx->chunk_prefix.p, n_chunks,
-                                  (const uint64_t *)ctx->row_prefix.p, (uint32_t *)ctx->order.p, s));
-    }
+    sh->units = units;
+    sh->max_p = max_p;
+    sh->n_order = sh->row_prefix[n];
+    sh->n_chunks = sh->chunk_prefix[n];
+}
+
+// Point each regrouped request at its segment of the row-order buffer.
+static void set_order(std::vector<ReqDesc> &reqs, const LaunchShape &sh, uint32_t *order) {
+    for (size_t i = 0; i < reqs.size(); ++i)
+        reqs[i].order = sh.row_prefix[i + 1] > sh.row_prefix[i] ? order + sh.row_prefix[i] : nullptr;
+}
+
+SweepParams sweep_params(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const ReqDesc *req,
+                         uint32_t n_req, uint64_t units, uint64_t surv_cap) {
     SweepParams P;
     memset(&P, 0, sizeof(P));
     P.K = ds.K;
@@ -347,8 +332,8 @@ int launch_reqs(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboi
     P.deep = (const DeepPrime *)ds.deep.p;
     P.vpool = (const uint8_t *)pl.vpool.p;
     P.ipool = (const uint16_t *)pl.ipool.p;
-    P.req = (const ReqDesc *)ctx->reqbuf.p;
-    P.n_req = n;
+    P.req = req;
+    P.n_req = n_req;
     P.n_units = units;
     P.counts = (unsigned long long *)ctx->counts.p;
     P.pairs = (unsigned long long *)ctx->pairs.p;
@@ -358,14 +343,49 @@ int launch_reqs(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboi
     P.surv = (SurvEntry *)ctx->surv.p;
     P.surv_cap = surv_cap;
     P.surv_n = (unsigned long long *)ctx->surv_n.p;
+    return P;
+}
+
+// One sweep launch over `reqs` (already holding row pointers), accumulating
+// into the context's count / pair / survivor buffers (zeroed by the caller).
+// Request j of this launch uses counter slot slot0 + j and survivor request
+// number slot0 + j.
+int launch_reqs(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid_tuning &tun,
+                std::vector<ReqDesc> &reqs, uint32_t slot0, uint64_t surv_cap, hipStream_t s,
+                uint64_t *units_out) {
+    const uint32_t n = (uint32_t)reqs.size();
+    LaunchShape sh;
+    shape_reqs(ctx, reqs, slot0, &sh);
+    if (sh.n_order) HIPCHK(ctx->order.ensure(sh.n_order * 4));
+    set_order(reqs, sh, (uint32_t *)ctx->order.p);
+    // staged through pinned memory; the previous user of the staging buffer
+    // on this stream has completed once the stream is idle
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(ctx->req_stage.ensure(n * sizeof(ReqDesc) + 2 * (n + 1) * 8));
+    unsigned char *stage = (unsigned char *)ctx->req_stage.p;
+    memcpy(stage, reqs.data(), n * sizeof(ReqDesc));
+    HIPCHK(ctx->reqbuf.ensure(n * sizeof(ReqDesc)));
+    HIPCHK(hipMemcpyAsync(ctx->reqbuf.p, stage, n * sizeof(ReqDesc), hipMemcpyHostToDevice, s));
+    if (sh.n_order) {
+        uint64_t *pre = (uint64_t *)(stage + n * sizeof(ReqDesc));
+        memcpy(pre, sh.chunk_prefix.data(), (n + 1) * 8);
+        memcpy(pre + n + 1, sh.row_prefix.data(), (n + 1) * 8);
+        HIPCHK(ctx->chunk_prefix.ensure((n + 1) * 8));
+        HIPCHK(ctx->row_prefix.ensure((n + 1) * 8));
+        HIPCHK(hipMemcpyAsync(ctx->chunk_prefix.p, pre, (n + 1) * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(ctx->row_prefix.p, pre + n + 1, (n + 1) * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(launch_bucket_rows((const ReqDesc *)ctx->reqbuf.p, n,
+                                  (const uint64_t *)ctx->chunk_prefix.p, sh.n_chunks,
+                                  (const uint64_t *)ctx->row_prefix.p, (uint32_t *)ctx->order.p, s));
+    }
+    const SweepParams P =
+        sweep_params(ctx, pl, ds, (const ReqDesc *)ctx->reqbuf.p, n, sh.units, surv_cap);
     const size_t lds = (size_t)ds.words * 8 + kSweepFixedLds;
     if (lds > ctx->max_lds) return CUBOID_E_LIMIT;
     if (ctx->timing) HIPCHK(hipEventRecord(ctx->ev_sweep0, s));
-    uint32_t max_p = 0;
-    for (const auto &r : reqs) max_p = std::max(max_p, r.p1);
-    HIPCHK(launch_sweep(P, (int)tun.workgroups, lds, max_p, s));
+    HIPCHK(launch_sweep(P, (int)tun.workgroups, lds, sh.max_p, s));
     if (ctx->timing) HIPCHK(hipEventRecord(ctx->ev_sweep1, s));
-    *units_out = units;
+    *units_out = sh.units;
     return CUBOID_OK;
 }
 
@@ -461,12 +481,21 @@ int sieve_rects(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes,
         if (st) return st;
     }
     if (ctx->timing) HIPCHK(hipEventRecord(ctx->ev_total0, s));
-    st = zero_scratch(ctx, n_req, nc, s);
-    if (st) return st;
     uint64_t units_total = 0;
     double sweep_ms = 0;
+    const size_t ncount = (size_t)n_req * nc;
+    ctx->last_graph = 0;
+    auto sweep_time = [&]() -> int {
+        if (!ctx->timing) return CUBOID_OK;
+        HIPCHK(hipEventSynchronize(ctx->ev_sweep1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, ctx->ev_sweep0, ctx->ev_sweep1));
+        sweep_ms += ms;
+        return CUBOID_OK;
+    };
+    std::vector<ReqDesc> reqs;
     if (resident) {
-        std::vector<ReqDesc> reqs(n_req);
+        reqs.resize(n_req);
         for (uint32_t i = 0; i < n_req; ++i) {
             ReqDesc &d = reqs[i];
             memset(&d, 0, sizeof(d));
@@ -476,58 +505,63 @@ int sieve_rects(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes,
             d.rows_p0 = 1;
             d.ip0 = rects[i].p0;
         }
-        st = launch_reqs(ctx, *pl, *ds, tun, reqs, 0, surv_cap, s, &units_total);
+    }
+    if (resident && ctx->use_graphs) {
+        // clears, sweep, replica sums and downloads all inside the graph
+        st = run_batch_graph(ctx, *pl, *ds, tun, reqs, surv_cap, s, &units_total);
         if (st) return st;
-        if (ctx->timing) {
-            HIPCHK(hipEventSynchronize(ctx->ev_sweep1));
-            float ms = 0;
-            HIPCHK(hipEventElapsedTime(&ms, ctx->ev_sweep0, ctx->ev_sweep1));
-            sweep_ms += ms;
-        }
+        HIPCHK(hipStreamSynchronize(s));
+        st = sweep_time();
+        if (st) return st;
     } else {
-        // bands of rows with their factors computed per band; one request at
-        // a time, each band keeping the request's number for its counters
-        for (uint32_t i = 0; i < n_req; ++i) {
-            const cuboid_request &rc = rects[i];
-            for (uint64_t b0 = rc.p0; b0 <= rc.p1; b0 += kBandRows) {
-                const uint64_t b1 = std::min<uint64_t>(rc.p1, b0 + kBandRows - 1);
-                HIPCHK(ctx->band_rows.ensure((b1 - b0 + 1) * sizeof(RowInfo)));
-                HIPCHK(ctx->band_nfac.ensure(b1 - b0 + 1));
-                HIPCHK(launch_row_info((const uint32_t *)ctx->primes16.p,
-                                       (const uint32_t *)ctx->magic16.p, ctx->n16, (uint32_t)b0,
-                                       b1 - b0 + 1, (RowInfo *)ctx->band_rows.p,
-                                       (uint8_t *)ctx->band_nfac.p, s));
-                std::vector<ReqDesc> reqs(1);
-                ReqDesc &d = reqs[0];
-                memset(&d, 0, sizeof(d));
-                d.p0 = (uint32_t)b0; d.p1 = (uint32_t)b1; d.q0 = rc.q0; d.q1 = rc.q1;
-                d.rows = (const RowInfo *)ctx->band_rows.p;
-                d.nfac = (const uint8_t *)ctx->band_nfac.p;
-                d.rows_p0 = (uint32_t)b0;
-                d.ip0 = rc.p0;
-                uint64_t units = 0;
-                st = launch_reqs(ctx, *pl, *ds, tun, reqs, i, surv_cap, s, &units);
-                if (st) return st;
-                units_total += units;
-                if (ctx->timing) {
-                    HIPCHK(hipEventSynchronize(ctx->ev_sweep1));
-                    float ms = 0;
-                    HIPCHK(hipEventElapsedTime(&ms, ctx->ev_sweep0, ctx->ev_sweep1));
-                    sweep_ms += ms;
+        st = zero_scratch(ctx, n_req, nc, s);
+        if (st) return st;
+        if (resident) {
+            st = launch_reqs(ctx, *pl, *ds, tun, reqs, 0, surv_cap, s, &units_total);
+            if (st) return st;
+            st = sweep_time();
+            if (st) return st;
+        } else {
+            // bands of rows with their factors computed per band; one request
+            // at a time, each band keeping the request's number for its counters
+            for (uint32_t i = 0; i < n_req; ++i) {
+                const cuboid_request &rc = rects[i];
+                for (uint64_t b0 = rc.p0; b0 <= rc.p1; b0 += kBandRows) {
+                    const uint64_t b1 = std::min<uint64_t>(rc.p1, b0 + kBandRows - 1);
+                    HIPCHK(ctx->band_rows.ensure((b1 - b0 + 1) * sizeof(RowInfo)));
+                    HIPCHK(ctx->band_nfac.ensure(b1 - b0 + 1));
+                    HIPCHK(launch_row_info((const uint32_t *)ctx->primes16.p,
+                                           (const uint32_t *)ctx->magic16.p, ctx->n16,
+                                           (uint32_t)b0, b1 - b0 + 1, (RowInfo *)ctx->band_rows.p,
+                                           (uint8_t *)ctx->band_nfac.p, s));
+                    std::vector<ReqDesc> band(1);
+                    ReqDesc &d = band[0];
+                    memset(&d, 0, sizeof(d));
+                    d.p0 = (uint32_t)b0; d.p1 = (uint32_t)b1; d.q0 = rc.q0; d.q1 = rc.q1;
+                    d.rows = (const RowInfo *)ctx->band_rows.p;
+                    d.nfac = (const uint8_t *)ctx->band_nfac.p;
+                    d.rows_p0 = (uint32_t)b0;
+                    d.ip0 = rc.p0;
+                    uint64_t units = 0;
+                    st = launch_reqs(ctx, *pl, *ds, tun, band, i, surv_cap, s, &units);
+                    if (st) return st;
+                    units_total += units;
+                    st = sweep_time();
+                    if (st) return st;
                 }
             }
         }
+        st = reduce_scratch(ctx, n_req, nc, s);
+        if (st) return st;
+        // results through pinned staging: counts, pairs, survivor count
+        HIPCHK(ctx->result_stage.ensure((ncount + n_req + 1) * 8));
+        uint64_t *rs = (uint64_t *)ctx->result_stage.p;
+        HIPCHK(hipMemcpyAsync(rs, ctx->counts.p, ncount * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(rs + ncount, ctx->pairs.p, (size_t)n_req * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(rs + ncount + n_req, ctx->surv_n.p, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
     }
-    st = reduce_scratch(ctx, n_req, nc, s);
-    if (st) return st;
-    // results through pinned staging: counts, pairs, survivor count
-    const size_t ncount = (size_t)n_req * nc;
-    HIPCHK(ctx->result_stage.ensure((ncount + n_req + 1) * 8));
-    uint64_t *stage = (uint64_t *)ctx->result_stage.p;
-    HIPCHK(hipMemcpyAsync(stage, ctx->counts.p, ncount * 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(stage + ncount, ctx->pairs.p, (size_t)n_req * 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(stage + ncount + n_req, ctx->surv_n.p, 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    const uint64_t *stage = (const uint64_t *)ctx->result_stage.p;
     const uint64_t nsurv = stage[ncount + n_req];
     const uint32_t np = (uint32_t)caller_primes.size();
     const std::vector<int32_t> col = count_columns(*pl, caller_primes);
@@ -556,6 +590,7 @@ int sieve_rects(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes,
         ctx->last.units = units_total;
         ctx->last.dense_primes = ds->K;
         ctx->last.workgroups = tun.workgroups;
+        ctx->last.graph = ctx->last_graph;
     }
     if (nsurv > surv_cap && surv_cap < surv_cap_total) return CUBOID_E_LIMIT;
     return CUBOID_OK;

@@ -1,0 +1,258 @@
+// Batched sieve as one HIP graph launch.
+//
+// A batch over resident rows is the fixed sequence: upload of the request
+// block, clears of the counter replicas and survivor count, regrouping of rows
+// by factor count, the sweep, the replica sums, and the download of counts,
+// pair counts and survivor count.  The sizes that vary from batch to batch
+// (unit count, regrouping chunks) travel in the request block's header and the
+// kernels read them from there, so one captured graph serves every batch with
+// the same request count, tables, tuning and buffers.  Graphs are cached per
+// context (least recently used out) and keyed by every pointer and size they
+// bake in.
+//
+// The graph is a parent of three captured parts (before / sweep / after) so
+// that event-record nodes can bracket the sweep for per-call kernel timing.
+// Clears are fill kernels: no memset nodes.
+#include <string.h>
+
+#include <algorithm>
+
+#include "runtime.h"
+
+namespace cuboid {
+
+namespace {
+
+constexpr size_t kHdrBytes = 32;         // unit count, chunk count, two unused words
+constexpr uint32_t kBucketGrid = 1024;   // blocks of the regrouping node (grid-stride)
+constexpr size_t kMaxGraphs = 8;         // cached graphs per context
+constexpr uint64_t kMinOrderRows = 1u << 20;
+
+struct Layout {
+    size_t o_desc, o_cpre, o_rpre, bytes;
+};
+
+// Request block, identical in pinned staging and on the device:
+// header | descriptors [n] | chunk prefix [n + 1] | row prefix [n + 1]
+Layout layout_of(uint32_t n) {
+    Layout L;
+    L.o_desc = kHdrBytes;
+    L.o_cpre = L.o_desc + (size_t)n * sizeof(ReqDesc);
+    L.o_rpre = L.o_cpre + (size_t)(n + 1) * 8;
+    L.bytes = L.o_rpre + (size_t)(n + 1) * 8;
+    return L;
+}
+
+template <typename T>
+void put(std::vector<unsigned char> *k, const T &v) {
+    const unsigned char *b = (const unsigned char *)&v;
+    k->insert(k->end(), b, b + sizeof(T));
+}
+
+template <typename F>
+hipError_t capture_part(hipStream_t s, hipGraph_t *g, F record) {
+    *g = nullptr;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const hipError_t e1 = record();
+    const hipError_t e2 = hipStreamEndCapture(s, g);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        if (*g) (void)hipGraphDestroy(*g);
+        *g = nullptr;
+        return e1 != hipSuccess ? e1 : e2;
+    }
+    return hipSuccess;
+}
+
+struct GraphArgs {
+    SweepParams P;
+    unsigned char *block;
+    const unsigned char *stage;
+    uint64_t *result;
+    uint32_t *order;
+    Layout L;
+    uint32_t n, nc, grid;
+    size_t lds;
+    uint32_t max_p;
+    bool timing;
+};
+
+hipError_t build_graph(cuboid_ctx *ctx, const GraphArgs &a, hipStream_t s, BatchGraph *out) {
+    const uint32_t n = a.n, nc = a.nc;
+    const uint64_t ncount = (uint64_t)n * nc;
+    hipGraph_t pre = nullptr, sweep = nullptr, post = nullptr, parent = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = capture_part(s, &pre, [&]() -> hipError_t {
+        hipError_t r = hipMemcpyAsync(a.block, a.stage, a.L.bytes, hipMemcpyHostToDevice, s);
+        if (r == hipSuccess) r = launch_fill_u64((uint64_t *)ctx->counts.p, (uint64_t)ctx->n_rep * ncount, 0, s);
+        if (r == hipSuccess) r = launch_fill_u64((uint64_t *)ctx->pairs.p, (uint64_t)ctx->n_rep * n, 0, s);
+        if (r == hipSuccess) r = launch_fill_u64((uint64_t *)ctx->surv_n.p, 1, 0, s);
+        if (r == hipSuccess)
+            r = launch_bucket_rows((const ReqDesc *)(a.block + a.L.o_desc), n,
+                                   (const uint64_t *)(a.block + a.L.o_cpre), 0,
+                                   (const uint64_t *)(a.block + a.L.o_rpre), a.order, s,
+                                   (const uint64_t *)a.block + 1, kBucketGrid);
+        return r;
+    });
+    if (e == hipSuccess)
+        e = capture_part(s, &sweep, [&]() { return launch_sweep(a.P, (int)a.grid, a.lds, a.max_p, s); });
+    if (e == hipSuccess)
+        e = capture_part(s, &post, [&]() -> hipError_t {
+            hipError_t r = launch_reduce_replicas((unsigned long long *)ctx->counts.p, ncount,
+                                                  ctx->n_rep, ctx->rep_stride_counts, s);
+            if (r == hipSuccess)
+                r = launch_reduce_replicas((unsigned long long *)ctx->pairs.p, n, ctx->n_rep,
+                                           ctx->rep_stride_pairs, s);
+            // no counters when every prime is trivial; capture refuses empty copies
+            if (r == hipSuccess && ncount)
+                r = hipMemcpyAsync(a.result, ctx->counts.p, ncount * 8, hipMemcpyDeviceToHost, s);
+            if (r == hipSuccess)
+                r = hipMemcpyAsync(a.result + ncount, ctx->pairs.p, (size_t)n * 8,
+                                   hipMemcpyDeviceToHost, s);
+            if (r == hipSuccess)
+                r = hipMemcpyAsync(a.result + ncount + n, ctx->surv_n.p, 8, hipMemcpyDeviceToHost, s);
+            return r;
+        });
+    if (e == hipSuccess) e = hipGraphCreate(&parent, 0);
+    if (e == hipSuccess) {
+        hipGraphNode_t prev = nullptr, node = nullptr;
+        e = hipGraphAddChildGraphNode(&node, parent, nullptr, 0, pre);
+        prev = node;
+        if (e == hipSuccess && a.timing) {
+            e = hipGraphAddEventRecordNode(&node, parent, &prev, 1, ctx->ev_sweep0);
+            prev = node;
+        }
+        if (e == hipSuccess) {
+            e = hipGraphAddChildGraphNode(&node, parent, &prev, 1, sweep);
+            prev = node;
+        }
+        if (e == hipSuccess && a.timing) {
+            e = hipGraphAddEventRecordNode(&node, parent, &prev, 1, ctx->ev_sweep1);
+            prev = node;
+        }
+        if (e == hipSuccess) e = hipGraphAddChildGraphNode(&node, parent, &prev, 1, post);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, parent, nullptr, nullptr, 0);
+    if (pre) (void)hipGraphDestroy(pre);
+    if (sweep) (void)hipGraphDestroy(sweep);
+    if (post) (void)hipGraphDestroy(post);
+    if (e != hipSuccess) {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (parent) (void)hipGraphDestroy(parent);
+        return e;
+    }
+    out->graph = parent;
+    out->exec = exec;
+    return hipSuccess;
+}
+
+}  // namespace
+
+void destroy_graph(BatchGraph *g) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    g->exec = nullptr;
+    g->graph = nullptr;
+}
+
+void drop_graphs(cuboid_ctx *ctx) {
+    for (auto &g : ctx->graphs) destroy_graph(&g);
+    ctx->graphs.clear();
+}
+
+// Resident-row batch as one graph launch on `s`; the caller synchronizes `s`
+// before reading counts, pair counts and the survivor count from the result
+// staging ([n * nc] counts | [n] pairs | survivor count).
+int run_batch_graph(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid_tuning &tun,
+                    std::vector<ReqDesc> &reqs, uint64_t surv_cap, hipStream_t s,
+                    uint64_t *units_out) {
+    const uint32_t n = (uint32_t)reqs.size();
+    const uint32_t nc = ds.K + ds.n_deep;
+    LaunchShape sh;
+    shape_reqs(ctx, reqs, 0, &sh);
+    if (sh.n_order) {
+        // room to spare so later batches keep the same buffer (and graph)
+        uint64_t want = kMinOrderRows;
+        while (want < sh.n_order) want <<= 1;
+        if (ctx->order.ensure(want * 4) != hipSuccess) return CUBOID_E_DEVICE;
+    }
+    for (size_t i = 0; i < reqs.size(); ++i)
+        reqs[i].order = sh.row_prefix[i + 1] > sh.row_prefix[i]
+                            ? (const uint32_t *)ctx->order.p + sh.row_prefix[i] : nullptr;
+    const size_t lds = (size_t)ds.words * 8 + kSweepFixedLds;
+    if (lds > ctx->max_lds) return CUBOID_E_LIMIT;
+    const Layout L = layout_of(n);
+    const uint64_t ncount = (uint64_t)n * nc;
+    // the previous reader of the staging buffers on this stream is done once
+    // the stream is idle
+    if (hipStreamSynchronize(s) != hipSuccess) return CUBOID_E_DEVICE;
+    if (ctx->gstage.ensure(L.bytes) != hipSuccess || ctx->gblock.ensure(L.bytes) != hipSuccess ||
+        ctx->result_stage.ensure((ncount + n + 1) * 8) != hipSuccess)
+        return CUBOID_E_DEVICE;
+    unsigned char *st = (unsigned char *)ctx->gstage.p;
+    const uint64_t hdr[4] = {sh.units, sh.n_chunks, 0, 0};
+    memcpy(st, hdr, sizeof(hdr));
+    memcpy(st + L.o_desc, reqs.data(), (size_t)n * sizeof(ReqDesc));
+    memcpy(st + L.o_cpre, sh.chunk_prefix.data(), (size_t)(n + 1) * 8);
+    memcpy(st + L.o_rpre, sh.row_prefix.data(), (size_t)(n + 1) * 8);
+
+    GraphArgs a;
+    a.block = (unsigned char *)ctx->gblock.p;
+    a.stage = st;
+    a.result = (uint64_t *)ctx->result_stage.p;
+    a.order = (uint32_t *)ctx->order.p;
+    a.L = L;
+    a.n = n;
+    a.nc = nc;
+    a.grid = tun.workgroups;
+    a.lds = lds;
+    a.max_p = sh.max_p;
+    a.timing = ctx->timing;
+    a.P = sweep_params(ctx, pl, ds, (const ReqDesc *)(a.block + L.o_desc), n, 0, surv_cap);
+    a.P.units_dev = (const unsigned long long *)a.block;
+
+    std::vector<unsigned char> key;
+    put(&key, a.P);
+    put(&key, (const void *)a.block);
+    put(&key, (const void *)a.stage);
+    put(&key, (const void *)a.result);
+    put(&key, (const void *)a.order);
+    put(&key, (uint64_t)L.bytes);
+    put(&key, (uint64_t)a.lds);
+    put(&key, ctx->n_rep);
+    put(&key, a.grid);
+    put(&key, (uint32_t)sweep_factor_slots(sh.max_p));
+    put(&key, (uint32_t)a.timing);
+    put(&key, (const void *)ctx->ev_sweep0);
+    put(&key, (const void *)ctx->ev_sweep1);
+
+    BatchGraph *g = nullptr;
+    for (auto &c : ctx->graphs)
+        if (c.key == key) g = &c;
+    ctx->last_graph = 1;
+    if (!g) {
+        if (ctx->graphs.size() >= kMaxGraphs) {
+            auto lru = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
+                                        [](const BatchGraph &x, const BatchGraph &y) {
+                                            return x.last_use < y.last_use;
+                                        });
+            destroy_graph(&*lru);
+            ctx->graphs.erase(lru);
+        }
+        BatchGraph fresh;
+        if (build_graph(ctx, a, s, &fresh) != hipSuccess) {
+            (void)hipGetLastError();
+            return CUBOID_E_DEVICE;
+        }
+        fresh.key = std::move(key);
+        ctx->graphs.push_back(std::move(fresh));
+        g = &ctx->graphs.back();
+        ctx->last_graph = 2;
+    }
+    g->last_use = ++ctx->graph_clock;
+    if (hipGraphLaunch(g->exec, s) != hipSuccess) return CUBOID_E_DEVICE;
+    *units_out = sh.units;
+    return CUBOID_OK;
+}
+
+}  // namespace cuboid

@@ -93,6 +93,7 @@ struct SweepParams {
     SurvEntry *surv;
     unsigned long long surv_cap;
     unsigned long long *surv_n;
+    const unsigned long long *units_dev; // if set, the unit count is read here, not n_units
 };
 
 // LDS bytes the sweep needs beyond the dense tables.
@@ -131,7 +132,8 @@ hipError_t launch_row_info(const uint32_t *primes16, const uint32_t *magic16, ui
 // regroup each request's rows, chunk by chunk, by number of factors >= 7
 hipError_t launch_bucket_rows(const ReqDesc *req, uint32_t n_req, const uint64_t *chunk_prefix,
                               uint64_t n_chunks, const uint64_t *row_prefix, uint32_t *order,
-                              hipStream_t s);
+                              hipStream_t s, const uint64_t *n_chunks_dev = nullptr,
+                              uint32_t grid = 0);
 // zero all replicas of the listed counter slots; sum them into out[i][nc + 1]
 hipError_t launch_zero_slots(unsigned long long *counts, unsigned long long *pairs,
                              const uint32_t *slots, uint32_t n, uint32_t nc, uint32_t n_rep,
@@ -144,6 +146,8 @@ hipError_t launch_reduce_slots(const unsigned long long *counts, const unsigned 
 hipError_t launch_reduce_replicas(unsigned long long *buf, uint64_t n, uint32_t n_rep,
                                   uint64_t stride, hipStream_t s);
 // max_p: the largest row coordinate of the launch (selects the factor slots)
+// factor slots the sweep reserves per row for rows up to max_p (4, 5 or 7)
+int sweep_factor_slots(uint32_t max_p);
 hipError_t launch_sweep(const SweepParams &P, int grid, size_t lds_bytes, uint32_t max_p,
                         hipStream_t s);
 hipError_t sweep_max_lds(size_t *bytes);

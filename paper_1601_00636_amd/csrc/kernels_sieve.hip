@@ -130,7 +130,8 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
     const uint32_t pat_byte = wheel_byte + kWheelSubsets * kWheel * 8;
     const uint64_t nwaves = (uint64_t)gridDim.x * kWavesPerWG;
     const uint64_t w = (uint64_t)blockIdx.x * kWavesPerWG + wv;
-    const uint64_t qd = P.n_units / nwaves, rd = P.n_units % nwaves;
+    const uint64_t n_units = P.units_dev ? uni64(*P.units_dev) : P.n_units;
+    const uint64_t qd = n_units / nwaves, rd = n_units % nwaves;
     uint64_t u = uni64(qd * w + (rd * w) / nwaves);
     const uint64_t uend = uni64(qd * (w + 1) + (rd * (w + 1)) / nwaves);
     if (u >= uend) return;
@@ -383,14 +384,18 @@ __global__ void merge_pass_kernel(const SurvEntry *src, SurvEntry *dst,
 
 }  // namespace
 
+// a row below 7*11*13*17*19 has at most 4 distinct primes >= 7, below
+// 7*11*13*17*19*23 at most 5, any uint32 at most 7
+int sweep_factor_slots(uint32_t max_p) {
+    return max_p < 323323u ? 4 : (max_p < 7436429u ? 5 : 7);
+}
+
 hipError_t launch_sweep(const SweepParams &P, int grid, size_t lds_bytes, uint32_t max_p,
                         hipStream_t s) {
     if (P.K > (uint32_t)kKMax) return hipErrorInvalidValue;
-    if (P.n_units == 0) return hipSuccess;
+    if (P.n_units == 0 && !P.units_dev) return hipSuccess;
     const dim3 g(grid), b(kWave * kWavesPerWG);
-    // factor slots: a row below 7*11*13*17*19 has at most 4 distinct primes
-    // >= 7, below 7*11*13*17*19*23 at most 5, any uint32 at most 7
-    const int mf = max_p < 323323u ? 4 : (max_p < 7436429u ? 5 : 7);
+    const int mf = sweep_factor_slots(max_p);
 #define CUBOID_SWEEP_K(k)                                                                      \
     case k:                                                                                    \
         if (mf == 4) hipLaunchKernelGGL((sweep_kernel<k, 4>), g, b, lds_bytes, s, P);           \

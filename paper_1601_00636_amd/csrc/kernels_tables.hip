@@ -235,29 +235,33 @@ __global__ void row_info_kernel(const uint32_t *primes16, const uint32_t *magic1
 __global__ void __launch_bounds__(256) bucket_rows_kernel(const ReqDesc *req, uint32_t n_req,
                                                           const uint64_t *chunk_prefix,
                                                           const uint64_t *row_prefix,
-                                                          uint32_t *order) {
+                                                          uint32_t *order, uint64_t n_chunks,
+                                                          const uint64_t *n_chunks_dev) {
     __shared__ uint32_t cnt[kMaxBigFactors + 1];
-    const uint64_t b = blockIdx.x;
-    const uint32_t i = find_segment(chunk_prefix, n_req, b);
-    const ReqDesc R = req[i];
-    const uint64_t rows = (uint64_t)R.p1 - R.p0 + 1;
-    const uint64_t r0 = (b - chunk_prefix[i]) * kBucketChunk;
-    const uint64_t r1 = r0 + kBucketChunk < rows ? r0 + kBucketChunk : rows;
-    if (threadIdx.x <= (unsigned)kMaxBigFactors) cnt[threadIdx.x] = 0;
-    __syncthreads();
-    for (uint64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x)
-        atomicAdd(&cnt[R.nfac[R.p0 + (uint32_t)r - R.rows_p0]], 1u);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t acc = 0;
-        for (int k = 0; k <= kMaxBigFactors; ++k) { const uint32_t c = cnt[k]; cnt[k] = acc; acc += c; }
-    }
-    __syncthreads();
-    uint32_t *dst = order + row_prefix[i] + r0;
-    for (uint64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-        const uint32_t p = R.p0 + (uint32_t)r;
-        const uint32_t pos = atomicAdd(&cnt[R.nfac[p - R.rows_p0]], 1u);
-        dst[pos] = p;
+    const uint64_t nch = n_chunks_dev ? *n_chunks_dev : n_chunks;
+    for (uint64_t b = blockIdx.x; b < nch; b += gridDim.x) {
+        const uint32_t i = find_segment(chunk_prefix, n_req, b);
+        const ReqDesc R = req[i];
+        const uint64_t rows = (uint64_t)R.p1 - R.p0 + 1;
+        const uint64_t r0 = (b - chunk_prefix[i]) * kBucketChunk;
+        const uint64_t r1 = r0 + kBucketChunk < rows ? r0 + kBucketChunk : rows;
+        if (threadIdx.x <= (unsigned)kMaxBigFactors) cnt[threadIdx.x] = 0;
+        __syncthreads();
+        for (uint64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x)
+            atomicAdd(&cnt[R.nfac[R.p0 + (uint32_t)r - R.rows_p0]], 1u);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t acc = 0;
+            for (int k = 0; k <= kMaxBigFactors; ++k) { const uint32_t c = cnt[k]; cnt[k] = acc; acc += c; }
+        }
+        __syncthreads();
+        uint32_t *dst = order + row_prefix[i] + r0;
+        for (uint64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+            const uint32_t p = R.p0 + (uint32_t)r;
+            const uint32_t pos = atomicAdd(&cnt[R.nfac[p - R.rows_p0]], 1u);
+            dst[pos] = p;
+        }
+        __syncthreads();   // cnt is cleared for the next chunk of this block
     }
 }
 
@@ -398,10 +402,12 @@ uint32_t pattern_offset(uint32_t l) {
 
 hipError_t launch_bucket_rows(const ReqDesc *req, uint32_t n_req, const uint64_t *chunk_prefix,
                               uint64_t n_chunks, const uint64_t *row_prefix, uint32_t *order,
-                              hipStream_t s) {
-    if (!n_chunks) return hipSuccess;
-    hipLaunchKernelGGL(bucket_rows_kernel, dim3((unsigned)n_chunks), dim3(256), 0, s, req, n_req,
-                       chunk_prefix, row_prefix, order);
+                              hipStream_t s, const uint64_t *n_chunks_dev, uint32_t grid) {
+    if (!n_chunks_dev && !n_chunks) return hipSuccess;
+    const uint32_t g = n_chunks_dev ? grid : (uint32_t)n_chunks;
+    if (g == 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(bucket_rows_kernel, dim3(g), dim3(256), 0, s, req, n_req, chunk_prefix,
+                       row_prefix, order, n_chunks, n_chunks_dev);
     return hipGetLastError();
 }
 

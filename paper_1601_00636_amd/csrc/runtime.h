@@ -70,6 +70,21 @@ struct Plan {
     std::map<uint32_t, std::unique_ptr<DenseSet>> dense;
 };
 
+// Unit space and row regrouping of one sweep launch.
+struct LaunchShape {
+    uint64_t units = 0, n_order = 0, n_chunks = 0;
+    uint32_t max_p = 0;
+    std::vector<uint64_t> row_prefix, chunk_prefix;   // [n + 1]
+};
+
+// A captured batch launch with the bytes of every pointer and size it bakes in.
+struct BatchGraph {
+    std::vector<unsigned char> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;
+};
+
 }  // namespace cuboid
 
 struct cuboid_ctx {
@@ -103,10 +118,18 @@ struct cuboid_ctx {
     bool bucketing = true;
     cuboid::HostBuf req_stage, result_stage;
 
+    // captured batch launches
+    bool use_graphs = true;
+    std::vector<cuboid::BatchGraph> graphs;
+    uint64_t graph_clock = 0;
+    uint32_t last_graph = 0;            // 0 eager, 1 replayed, 2 captured for this call
+    cuboid::DevBuf gblock;              // request block read by the graph
+    cuboid::HostBuf gstage;             // its pinned staging
+
     // timing
     bool timing = false;
     hipEvent_t ev_sweep0 = nullptr, ev_sweep1 = nullptr, ev_total0 = nullptr, ev_total1 = nullptr;
-    cuboid_timing last = {0, 0, 0, 0, 0};
+    cuboid_timing last = {0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace cuboid {
@@ -131,6 +154,13 @@ struct SieveOut {
     std::vector<SurvEntry> surv;    // all survivors sorted by (request, index), if fetched
     uint64_t n_surv = 0;            // survivors of the whole call
 };
+void shape_reqs(cuboid_ctx *ctx, std::vector<ReqDesc> &reqs, uint32_t slot0, LaunchShape *sh);
+SweepParams sweep_params(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const ReqDesc *req,
+                         uint32_t n_req, uint64_t units, uint64_t surv_cap);
+int run_batch_graph(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid_tuning &tun,
+                    std::vector<ReqDesc> &reqs, uint64_t surv_cap, hipStream_t s,
+                    uint64_t *units_out);
+void drop_graphs(cuboid_ctx *ctx);
 int sieve_rects(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes,
                 const std::vector<cuboid_request> &rects, uint64_t surv_cap_total,
                 hipStream_t s, SieveOut *out);
