@@ -127,6 +127,34 @@ int cuboid_sieve_range(cuboid_ctx *ctx, uint32_t p0, uint32_t p1, uint32_t q0, u
                        uint64_t *counts, uint64_t *n_pairs, void *hip_stream);
 
 /*
+ * The sieve over region (1.2) of Theorem 1.2 for p0 <= p <= p1, the scan of
+ * sections 5 and 6: for each p every integer q with
+ * min(cbrt(p / 9), p / 59) <= q <= 59 p (the lower bound taken exactly: the
+ * smaller of the least q with 9 q^3 >= p and the least q with 59 q >= p), in
+ * the domain and with the first-rejecter counting of cuboid_sieve_range.
+ *
+ * Survivors are written as ascending uint64 values p * 2^32 + q.
+ * r_max (may be NULL) receives one value per report band of band_rows
+ * consecutive p starting at p0 (ceil((p1 - p0 + 1) / band_rows) entries; the
+ * paper reports per hundred): the largest prime some pair of the band was
+ * tested against, i.e. its deepest first rejecting prime, or the largest
+ * listed prime if a pair of the band passed every prime, or 1 if the band
+ * holds no pair.  The largest r_max over the bands is the depth the sieve
+ * reached (section 6: 137 for p <= 154000 with the primes 11..541).
+ *
+ * Limits: 1 <= p0 <= p1 <= 72796055 (so that 59 p < 2^32, the paper's 32-bit
+ * bound of section 6), band_rows >= 1.
+ * Errors: E_RANGE (p0 == 0 or p0 > p1), E_LIMIT (p1 > 72796055, or more
+ * survivors than the device list holds), E_ARG (band_rows == 0, a required
+ * pointer NULL), E_PRIMES, E_CAPACITY (as in cuboid_sieve_range), E_DEVICE,
+ * E_NOT_LOADED.
+ */
+int cuboid_sieve_region(cuboid_ctx *ctx, uint32_t p0, uint32_t p1, uint32_t band_rows,
+                        const uint32_t *primes, uint32_t n_primes,
+                        uint64_t *survivors, uint64_t cap, uint64_t *n_survivors,
+                        uint64_t *counts, uint64_t *n_pairs, uint32_t *r_max, void *hip_stream);
+
+/*
  * One positive integer root of Q_pq (eq. 1.1) confirmed in exact arithmetic.
  * flags: bit 0 t > p^2, bit 1 t > pq, bit 2 t > q^2,
  *        bit 3 (p^2 + t)(pq + t) > 2 t^2  (the inequalities of Theorem 1.1);

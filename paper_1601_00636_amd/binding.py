@@ -83,6 +83,8 @@ def _load():
         "cuboid_table_bytes": ([vp, u32, P(u8), ctypes.c_size_t, P(ctypes.c_size_t)], i32),
         "cuboid_sieve_range": ([vp, u32, u32, u32, u32, P(u32), u32, P(u64), u64, P(u64), P(u64),
                                 P(u64), vp], i32),
+        "cuboid_sieve_region": ([vp, u32, u32, u32, P(u32), u32, P(u64), u64, P(u64), P(u64),
+                                 P(u64), P(u32), vp], i32),
         "cuboid_root_check": ([vp, P(u32), P(u32), u64, P(cuboid_root), u64, P(u64)], i32),
         "cuboid_exact_check": ([u32, u32, u64, P(i32), P(u32)], i32),
         "cuboid_exact_value": ([u32, u32, u64, ctypes.c_char_p, ctypes.c_size_t], i32),
@@ -194,6 +196,25 @@ def cuboid_sieve_range(ctx, p0, p1, q0, q1, primes, cap=1 << 20, stream=None):
     _check(st, "cuboid_sieve_range", needed=ns.value if st == E_CAPACITY else None)
     return dict(counts=counts[:len(pr)], n_pairs=npairs.value, n_survivors=ns.value,
                 survivors=surv[:ns.value].copy())
+
+
+def cuboid_sieve_region(ctx, p0, p1, primes, band_rows=100, cap=1 << 16, stream=None):
+    """Region (1.2) for p0 <= p <= p1: dict(counts, n_pairs, n_survivors,
+    survivors as (p, q) pairs, r_max per band of band_rows rows)."""
+    pr = _arr(primes, np.uint32)
+    counts = np.zeros(max(1, len(pr)), dtype=np.uint64)
+    surv = np.zeros(max(1, cap), dtype=np.uint64)
+    n_bands = (int(p1) - int(p0) + band_rows) // band_rows if p1 >= p0 and band_rows else 1
+    rmax = np.zeros(max(1, n_bands), dtype=np.uint32)
+    ns, npairs = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    st = _load().cuboid_sieve_region(ctx, int(p0), int(p1), int(band_rows), _p(pr, u32), len(pr),
+                                     _p(surv, u64), int(cap), ctypes.byref(ns), _p(counts, u64),
+                                     ctypes.byref(npairs), _p(rmax, u32), _stream(stream))
+    _check(st, "cuboid_sieve_region", needed=ns.value if st == E_CAPACITY else None)
+    sv = surv[:ns.value]
+    return dict(counts=counts[:len(pr)], n_pairs=npairs.value, n_survivors=ns.value,
+                survivors=[(int(x >> np.uint64(32)), int(x & np.uint64(0xffffffff))) for x in sv],
+                r_max=rmax[:n_bands].copy())
 
 
 def cuboid_root_check(ctx, p, q, cap=1 << 16):

@@ -20,6 +20,7 @@ SOURCES = [
     "kernels_roots.hip",
     "bigint.cpp",
     "graph.cpp",
+    "region.cpp",
     "context.cpp",
     "autotune.cpp",
     "server.cpp",

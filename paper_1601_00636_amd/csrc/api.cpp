@@ -209,6 +209,26 @@ int cuboid_sieve_range(cuboid_ctx *ctx, uint32_t p0, uint32_t p1, uint32_t q0, u
     return CUBOID_OK;
 }
 
+int cuboid_sieve_region(cuboid_ctx *ctx, uint32_t p0, uint32_t p1, uint32_t band_rows,
+                        const uint32_t *primes, uint32_t n_primes, uint64_t *survivors,
+                        uint64_t cap, uint64_t *n_survivors, uint64_t *counts, uint64_t *n_pairs,
+                        uint32_t *r_max, void *hip_stream) {
+    if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
+    if (!n_survivors || !counts || !n_pairs || (cap && !survivors) || band_rows == 0)
+        return CUBOID_E_ARG;
+    if (p0 == 0 || p0 > p1) return CUBOID_E_RANGE;
+    if (p1 > kRegionMaxP) return CUBOID_E_LIMIT;
+    std::vector<uint32_t> sorted;
+    int st = canonical_primes(primes, n_primes, &sorted);
+    if (st) return st;
+    std::lock_guard<std::recursive_mutex> g(ctx->mu);
+    if (set_device(ctx)) return CUBOID_E_DEVICE;
+    const std::vector<uint32_t> caller(primes, primes + n_primes);
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    return region_sieve(ctx, p0, p1, band_rows, caller, survivors, cap, n_survivors, counts,
+                        n_pairs, r_max, s);
+}
+
 int cuboid_sieve_batch(cuboid_ctx *ctx, const cuboid_request *req, uint32_t n_req,
                        const uint32_t *primes, uint32_t n_primes, cuboid_result *res,
                        void *hip_stream) {

@@ -277,10 +277,10 @@ cuboid_tuning tuning_for(cuboid_ctx *ctx, const std::vector<uint32_t> &primes, c
     return t;
 }
 
-// Unit space of one launch: each request's first unit, unit count and counter
-// slot (slot0 + its position), and which requests get their rows regrouped by
-// factor count (prefix sums of regrouped rows and of 8192-row chunks).
-void shape_reqs(cuboid_ctx *ctx, std::vector<ReqDesc> &reqs, uint32_t slot0, LaunchShape *sh) {
+// Unit space of one launch: each request's first unit and unit count, and
+// which requests get their rows regrouped by factor count (prefix sums of
+// regrouped rows and of 8192-row chunks).  Counter slots are the caller's.
+void shape_reqs(cuboid_ctx *ctx, std::vector<ReqDesc> &reqs, LaunchShape *sh) {
     const uint32_t n = (uint32_t)reqs.size();
     sh->row_prefix.assign(n + 1, 0);
     sh->chunk_prefix.assign(n + 1, 0);
@@ -294,7 +294,6 @@ void shape_reqs(cuboid_ctx *ctx, std::vector<ReqDesc> &reqs, uint32_t slot0, Lau
         r.unit0 = units;
         r.ulo = 0;
         r.ucount = (uint64_t)r.nrb * r.nwin;
-        r.slot = slot0 + i;
         units += r.ucount;
         max_p = std::max(max_p, r.p1);
         const bool group = ctx->bucketing && rows >= kBucketMinRows &&
@@ -346,16 +345,15 @@ SweepParams sweep_params(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, co
     return P;
 }
 
-// One sweep launch over `reqs` (already holding row pointers), accumulating
-// into the context's count / pair / survivor buffers (zeroed by the caller).
-// Request j of this launch uses counter slot slot0 + j and survivor request
-// number slot0 + j.
+// One sweep launch over `reqs` (already holding row pointers and counter
+// slots), accumulating into the context's count / pair / survivor buffers
+// (zeroed by the caller).
 int launch_reqs(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid_tuning &tun,
-                std::vector<ReqDesc> &reqs, uint32_t slot0, uint64_t surv_cap, hipStream_t s,
+                std::vector<ReqDesc> &reqs, uint64_t surv_cap, hipStream_t s,
                 uint64_t *units_out) {
     const uint32_t n = (uint32_t)reqs.size();
     LaunchShape sh;
-    shape_reqs(ctx, reqs, slot0, &sh);
+    shape_reqs(ctx, reqs, &sh);
     if (sh.n_order) HIPCHK(ctx->order.ensure(sh.n_order * 4));
     set_order(reqs, sh, (uint32_t *)ctx->order.p);
     // staged through pinned memory; the previous user of the staging buffer
@@ -452,147 +450,186 @@ int rect_valid(uint32_t p0, uint32_t p1, uint32_t q0, uint32_t q1) {
     return CUBOID_OK;
 }
 
-// The plain and batched sieve share this path.  `rects` are validated.
-int sieve_rects(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes,
-                const std::vector<cuboid_request> &rects, uint64_t surv_cap_total,
-                hipStream_t s, SieveOut *out) {
-    std::vector<uint32_t> primes;
-    int st = canonical_primes(caller_primes.data(), (uint32_t)caller_primes.size(), &primes);
+// The sweep over descriptors whose p0, p1, q0, q1, ip0, slot and flags are
+// set; several descriptors may share a counter slot.  Rows come from the
+// resident table when every p fits it (one graph replay when graphs are on),
+// else from row windows of kBandRows rows computed on the fly, each
+// descriptor split at window edges.
+int sieve_core(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid_tuning &tun,
+               std::vector<ReqDesc> &reqs, uint32_t n_slots, uint64_t surv_cap, hipStream_t s,
+               CoreOut *out) {
+    const uint32_t nc = ds.K + ds.n_deep;
+    int st = ensure_scratch(ctx, n_slots, nc, surv_cap);
     if (st) return st;
-    Plan *pl = nullptr;
-    st = build_plan(ctx, primes, &pl);
-    if (st) return st;
-    const cuboid_tuning tun = tuning_for(ctx, primes, *pl);
-    DenseSet *ds = nullptr;
-    st = build_dense(ctx, pl, tun.dense_primes, &ds);
-    if (st) return st;
-    const uint32_t nc = ds->K + ds->n_deep;
-    const uint32_t n_req = (uint32_t)rects.size();
-    const uint64_t surv_cap = std::min<uint64_t>(surv_cap_total, kMaxSurvScratch);
-    st = ensure_scratch(ctx, n_req, nc, surv_cap);
-    if (st) return st;
-
-    // rows: resident table when every row fits below 2^24, else per-band scratch
     uint32_t pmax = 0;
-    for (auto &r : rects) pmax = std::max(pmax, r.p1);
+    for (auto &r : reqs) pmax = std::max(pmax, r.p1);
     const bool resident = pmax <= kResidentRowsMax;
     if (resident) {
         st = ensure_rows(ctx, pmax);
         if (st) return st;
     }
-    if (ctx->timing) HIPCHK(hipEventRecord(ctx->ev_total0, s));
-    uint64_t units_total = 0;
-    double sweep_ms = 0;
-    const size_t ncount = (size_t)n_req * nc;
+    out->units = 0;
+    out->sweep_ms = 0;
+    const size_t ncount = (size_t)n_slots * nc;
     ctx->last_graph = 0;
     auto sweep_time = [&]() -> int {
         if (!ctx->timing) return CUBOID_OK;
         HIPCHK(hipEventSynchronize(ctx->ev_sweep1));
         float ms = 0;
         HIPCHK(hipEventElapsedTime(&ms, ctx->ev_sweep0, ctx->ev_sweep1));
-        sweep_ms += ms;
+        out->sweep_ms += ms;
         return CUBOID_OK;
     };
-    std::vector<ReqDesc> reqs;
     if (resident) {
-        reqs.resize(n_req);
-        for (uint32_t i = 0; i < n_req; ++i) {
-            ReqDesc &d = reqs[i];
-            memset(&d, 0, sizeof(d));
-            d.p0 = rects[i].p0; d.p1 = rects[i].p1; d.q0 = rects[i].q0; d.q1 = rects[i].q1;
+        for (auto &d : reqs) {
             d.rows = (const RowInfo *)ctx->rows.p;
             d.nfac = (const uint8_t *)ctx->nfac.p;
             d.rows_p0 = 1;
-            d.ip0 = rects[i].p0;
         }
     }
     if (resident && ctx->use_graphs) {
         // clears, sweep, replica sums and downloads all inside the graph
-        st = run_batch_graph(ctx, *pl, *ds, tun, reqs, surv_cap, s, &units_total);
+        st = run_batch_graph(ctx, pl, ds, tun, reqs, n_slots, surv_cap, s, &out->units);
         if (st) return st;
         HIPCHK(hipStreamSynchronize(s));
         st = sweep_time();
         if (st) return st;
     } else {
-        st = zero_scratch(ctx, n_req, nc, s);
+        st = zero_scratch(ctx, n_slots, nc, s);
         if (st) return st;
         if (resident) {
-            st = launch_reqs(ctx, *pl, *ds, tun, reqs, 0, surv_cap, s, &units_total);
+            st = launch_reqs(ctx, pl, ds, tun, reqs, surv_cap, s, &out->units);
             if (st) return st;
             st = sweep_time();
             if (st) return st;
         } else {
-            // bands of rows with their factors computed per band; one request
-            // at a time, each band keeping the request's number for its counters
-            for (uint32_t i = 0; i < n_req; ++i) {
-                const cuboid_request &rc = rects[i];
-                for (uint64_t b0 = rc.p0; b0 <= rc.p1; b0 += kBandRows) {
-                    const uint64_t b1 = std::min<uint64_t>(rc.p1, b0 + kBandRows - 1);
-                    HIPCHK(ctx->band_rows.ensure((b1 - b0 + 1) * sizeof(RowInfo)));
-                    HIPCHK(ctx->band_nfac.ensure(b1 - b0 + 1));
-                    HIPCHK(launch_row_info((const uint32_t *)ctx->primes16.p,
-                                           (const uint32_t *)ctx->magic16.p, ctx->n16,
-                                           (uint32_t)b0, b1 - b0 + 1, (RowInfo *)ctx->band_rows.p,
-                                           (uint8_t *)ctx->band_nfac.p, s));
-                    std::vector<ReqDesc> band(1);
-                    ReqDesc &d = band[0];
-                    memset(&d, 0, sizeof(d));
-                    d.p0 = (uint32_t)b0; d.p1 = (uint32_t)b1; d.q0 = rc.q0; d.q1 = rc.q1;
-                    d.rows = (const RowInfo *)ctx->band_rows.p;
-                    d.nfac = (const uint8_t *)ctx->band_nfac.p;
-                    d.rows_p0 = (uint32_t)b0;
-                    d.ip0 = rc.p0;
-                    uint64_t units = 0;
-                    st = launch_reqs(ctx, *pl, *ds, tun, band, i, surv_cap, s, &units);
-                    if (st) return st;
-                    units_total += units;
-                    st = sweep_time();
-                    if (st) return st;
+            // pieces of each descriptor per row window, windows in ascending p
+            std::map<uint64_t, std::vector<ReqDesc>> win;
+            for (const ReqDesc &d : reqs) {
+                for (uint64_t a = d.p0; a <= d.p1;) {
+                    const uint64_t w = (a - 1) / kBandRows;
+                    const uint64_t b = std::min<uint64_t>(d.p1, (w + 1) * kBandRows);
+                    ReqDesc piece = d;
+                    piece.p0 = (uint32_t)a;
+                    piece.p1 = (uint32_t)b;
+                    win[w].push_back(piece);
+                    a = b + 1;
                 }
             }
+            for (auto &kv : win) {
+                std::vector<ReqDesc> &pieces = kv.second;
+                uint32_t lo = 0xffffffffu, hi = 0;
+                for (auto &d : pieces) { lo = std::min(lo, d.p0); hi = std::max(hi, d.p1); }
+                const uint64_t nrows = (uint64_t)hi - lo + 1;
+                HIPCHK(ctx->band_rows.ensure(nrows * sizeof(RowInfo)));
+                HIPCHK(ctx->band_nfac.ensure(nrows));
+                HIPCHK(launch_row_info((const uint32_t *)ctx->primes16.p,
+                                       (const uint32_t *)ctx->magic16.p, ctx->n16, lo, nrows,
+                                       (RowInfo *)ctx->band_rows.p, (uint8_t *)ctx->band_nfac.p, s));
+                for (auto &d : pieces) {
+                    d.rows = (const RowInfo *)ctx->band_rows.p;
+                    d.nfac = (const uint8_t *)ctx->band_nfac.p;
+                    d.rows_p0 = lo;
+                }
+                uint64_t units = 0;
+                st = launch_reqs(ctx, pl, ds, tun, pieces, surv_cap, s, &units);
+                if (st) return st;
+                out->units += units;
+                st = sweep_time();
+                if (st) return st;
+            }
         }
-        st = reduce_scratch(ctx, n_req, nc, s);
+        st = reduce_scratch(ctx, n_slots, nc, s);
         if (st) return st;
         // results through pinned staging: counts, pairs, survivor count
-        HIPCHK(ctx->result_stage.ensure((ncount + n_req + 1) * 8));
+        HIPCHK(ctx->result_stage.ensure((ncount + n_slots + 1) * 8));
         uint64_t *rs = (uint64_t *)ctx->result_stage.p;
-        HIPCHK(hipMemcpyAsync(rs, ctx->counts.p, ncount * 8, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(rs + ncount, ctx->pairs.p, (size_t)n_req * 8, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(rs + ncount + n_req, ctx->surv_n.p, 8, hipMemcpyDeviceToHost, s));
+        if (ncount)
+            HIPCHK(hipMemcpyAsync(rs, ctx->counts.p, ncount * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(rs + ncount, ctx->pairs.p, (size_t)n_slots * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(rs + ncount + n_slots, ctx->surv_n.p, 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
     }
     const uint64_t *stage = (const uint64_t *)ctx->result_stage.p;
-    const uint64_t nsurv = stage[ncount + n_req];
+    out->nc = nc;
+    out->n_slots = n_slots;
+    out->counts.assign(stage, stage + ncount);
+    out->pairs.assign(stage + ncount, stage + ncount + n_slots);
+    out->n_surv = stage[ncount + n_slots];
+    out->surv.clear();
+    if (out->n_surv > 0 && out->n_surv <= surv_cap) {
+        st = fetch_survivors(ctx, out->n_surv, &out->surv, s);
+        if (st) return st;
+    }
+    return CUBOID_OK;
+}
+
+// Canonical plan, tuning and dense tables of a caller's prime list.
+int prepare_primes(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes, Plan **pl,
+                   cuboid_tuning *tun, DenseSet **ds) {
+    std::vector<uint32_t> primes;
+    int st = canonical_primes(caller_primes.data(), (uint32_t)caller_primes.size(), &primes);
+    if (st) return st;
+    st = build_plan(ctx, primes, pl);
+    if (st) return st;
+    *tun = tuning_for(ctx, primes, **pl);
+    return build_dense(ctx, *pl, tun->dense_primes, ds);
+}
+
+void record_timing(cuboid_ctx *ctx, hipStream_t s, const CoreOut &co, const DenseSet &ds,
+                   const cuboid_tuning &tun) {
+    if (!ctx->timing) return;
+    if (hipEventRecord(ctx->ev_total1, s) != hipSuccess) return;
+    if (hipEventSynchronize(ctx->ev_total1) != hipSuccess) return;
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, ctx->ev_total0, ctx->ev_total1) != hipSuccess) return;
+    ctx->last.sweep_ms = co.sweep_ms;
+    ctx->last.total_gpu_ms = ms;
+    ctx->last.units = co.units;
+    ctx->last.dense_primes = ds.K;
+    ctx->last.workgroups = tun.workgroups;
+    ctx->last.graph = ctx->last_graph;
+}
+
+// The plain and batched sieve share this path.  `rects` are validated.
+int sieve_rects(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes,
+                const std::vector<cuboid_request> &rects, uint64_t surv_cap_total,
+                hipStream_t s, SieveOut *out) {
+    Plan *pl = nullptr;
+    DenseSet *ds = nullptr;
+    cuboid_tuning tun;
+    int st = prepare_primes(ctx, caller_primes, &pl, &tun, &ds);
+    if (st) return st;
+    const uint32_t n_req = (uint32_t)rects.size();
+    const uint64_t surv_cap = std::min<uint64_t>(surv_cap_total, kMaxSurvScratch);
+    std::vector<ReqDesc> reqs(n_req);
+    for (uint32_t i = 0; i < n_req; ++i) {
+        ReqDesc &d = reqs[i];
+        memset(&d, 0, sizeof(d));
+        d.p0 = rects[i].p0; d.p1 = rects[i].p1; d.q0 = rects[i].q0; d.q1 = rects[i].q1;
+        d.ip0 = rects[i].p0;
+        d.slot = i;
+    }
+    if (ctx->timing) HIPCHK(hipEventRecord(ctx->ev_total0, s));
+    CoreOut co;
+    st = sieve_core(ctx, *pl, *ds, tun, reqs, n_req, surv_cap, s, &co);
+    if (st) return st;
+    const uint32_t nc = co.nc;
     const uint32_t np = (uint32_t)caller_primes.size();
     const std::vector<int32_t> col = count_columns(*pl, caller_primes);
     out->n_req = n_req;
     out->n_primes = np;
-    out->n_surv = nsurv;
+    out->n_surv = co.n_surv;
     out->counts.assign((size_t)n_req * np, 0);
     for (uint32_t i = 0; i < n_req; ++i) {
-        const uint64_t *c = stage + (size_t)i * nc;
+        const uint64_t *c = co.counts.data() + (size_t)i * nc;
         uint64_t *o = out->counts.data() + (size_t)i * np;
         for (uint32_t j = 0; j < np; ++j) o[j] = col[j] < 0 ? 0 : c[col[j]];
     }
-    out->pairs.assign(stage + ncount, stage + ncount + n_req);
-    out->surv.clear();
-    if (nsurv > 0 && nsurv <= surv_cap) {
-        st = fetch_survivors(ctx, nsurv, &out->surv, s);
-        if (st) return st;
-    }
-    if (ctx->timing) {
-        HIPCHK(hipEventRecord(ctx->ev_total1, s));
-        HIPCHK(hipEventSynchronize(ctx->ev_total1));
-        float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, ctx->ev_total0, ctx->ev_total1));
-        ctx->last.sweep_ms = sweep_ms;
-        ctx->last.total_gpu_ms = ms;
-        ctx->last.units = units_total;
-        ctx->last.dense_primes = ds->K;
-        ctx->last.workgroups = tun.workgroups;
-        ctx->last.graph = ctx->last_graph;
-    }
-    if (nsurv > surv_cap && surv_cap < surv_cap_total) return CUBOID_E_LIMIT;
+    out->pairs = std::move(co.pairs);
+    out->surv = std::move(co.surv);
+    record_timing(ctx, s, co, *ds, tun);
+    if (co.n_surv > surv_cap && surv_cap < surv_cap_total) return CUBOID_E_LIMIT;
     return CUBOID_OK;
 }
 

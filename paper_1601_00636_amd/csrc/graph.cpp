@@ -71,21 +71,21 @@ struct GraphArgs {
     uint64_t *result;
     uint32_t *order;
     Layout L;
-    uint32_t n, nc, grid;
+    uint32_t n, n_slots, nc, grid;
     size_t lds;
     uint32_t max_p;
     bool timing;
 };
 
 hipError_t build_graph(cuboid_ctx *ctx, const GraphArgs &a, hipStream_t s, BatchGraph *out) {
-    const uint32_t n = a.n, nc = a.nc;
-    const uint64_t ncount = (uint64_t)n * nc;
+    const uint32_t n = a.n, ns = a.n_slots, nc = a.nc;
+    const uint64_t ncount = (uint64_t)ns * nc;
     hipGraph_t pre = nullptr, sweep = nullptr, post = nullptr, parent = nullptr;
     hipGraphExec_t exec = nullptr;
     hipError_t e = capture_part(s, &pre, [&]() -> hipError_t {
         hipError_t r = hipMemcpyAsync(a.block, a.stage, a.L.bytes, hipMemcpyHostToDevice, s);
         if (r == hipSuccess) r = launch_fill_u64((uint64_t *)ctx->counts.p, (uint64_t)ctx->n_rep * ncount, 0, s);
-        if (r == hipSuccess) r = launch_fill_u64((uint64_t *)ctx->pairs.p, (uint64_t)ctx->n_rep * n, 0, s);
+        if (r == hipSuccess) r = launch_fill_u64((uint64_t *)ctx->pairs.p, (uint64_t)ctx->n_rep * ns, 0, s);
         if (r == hipSuccess) r = launch_fill_u64((uint64_t *)ctx->surv_n.p, 1, 0, s);
         if (r == hipSuccess)
             r = launch_bucket_rows((const ReqDesc *)(a.block + a.L.o_desc), n,
@@ -101,16 +101,16 @@ hipError_t build_graph(cuboid_ctx *ctx, const GraphArgs &a, hipStream_t s, Batch
             hipError_t r = launch_reduce_replicas((unsigned long long *)ctx->counts.p, ncount,
                                                   ctx->n_rep, ctx->rep_stride_counts, s);
             if (r == hipSuccess)
-                r = launch_reduce_replicas((unsigned long long *)ctx->pairs.p, n, ctx->n_rep,
+                r = launch_reduce_replicas((unsigned long long *)ctx->pairs.p, ns, ctx->n_rep,
                                            ctx->rep_stride_pairs, s);
             // no counters when every prime is trivial; capture refuses empty copies
             if (r == hipSuccess && ncount)
                 r = hipMemcpyAsync(a.result, ctx->counts.p, ncount * 8, hipMemcpyDeviceToHost, s);
             if (r == hipSuccess)
-                r = hipMemcpyAsync(a.result + ncount, ctx->pairs.p, (size_t)n * 8,
+                r = hipMemcpyAsync(a.result + ncount, ctx->pairs.p, (size_t)ns * 8,
                                    hipMemcpyDeviceToHost, s);
             if (r == hipSuccess)
-                r = hipMemcpyAsync(a.result + ncount + n, ctx->surv_n.p, 8, hipMemcpyDeviceToHost, s);
+                r = hipMemcpyAsync(a.result + ncount + ns, ctx->surv_n.p, 8, hipMemcpyDeviceToHost, s);
             return r;
         });
     if (e == hipSuccess) e = hipGraphCreate(&parent, 0);
@@ -162,14 +162,14 @@ void drop_graphs(cuboid_ctx *ctx) {
 
 // Resident-row batch as one graph launch on `s`; the caller synchronizes `s`
 // before reading counts, pair counts and the survivor count from the result
-// staging ([n * nc] counts | [n] pairs | survivor count).
+// staging ([n_slots * nc] counts | [n_slots] pairs | survivor count).
 int run_batch_graph(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid_tuning &tun,
-                    std::vector<ReqDesc> &reqs, uint64_t surv_cap, hipStream_t s,
-                    uint64_t *units_out) {
+                    std::vector<ReqDesc> &reqs, uint32_t n_slots, uint64_t surv_cap,
+                    hipStream_t s, uint64_t *units_out) {
     const uint32_t n = (uint32_t)reqs.size();
     const uint32_t nc = ds.K + ds.n_deep;
     LaunchShape sh;
-    shape_reqs(ctx, reqs, 0, &sh);
+    shape_reqs(ctx, reqs, &sh);
     if (sh.n_order) {
         // room to spare so later batches keep the same buffer (and graph)
         uint64_t want = kMinOrderRows;
@@ -182,12 +182,12 @@ int run_batch_graph(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const c
     const size_t lds = (size_t)ds.words * 8 + kSweepFixedLds;
     if (lds > ctx->max_lds) return CUBOID_E_LIMIT;
     const Layout L = layout_of(n);
-    const uint64_t ncount = (uint64_t)n * nc;
+    const uint64_t ncount = (uint64_t)n_slots * nc;
     // the previous reader of the staging buffers on this stream is done once
     // the stream is idle
     if (hipStreamSynchronize(s) != hipSuccess) return CUBOID_E_DEVICE;
     if (ctx->gstage.ensure(L.bytes) != hipSuccess || ctx->gblock.ensure(L.bytes) != hipSuccess ||
-        ctx->result_stage.ensure((ncount + n + 1) * 8) != hipSuccess)
+        ctx->result_stage.ensure((ncount + n_slots + 1) * 8) != hipSuccess)
         return CUBOID_E_DEVICE;
     unsigned char *st = (unsigned char *)ctx->gstage.p;
     const uint64_t hdr[4] = {sh.units, sh.n_chunks, 0, 0};
@@ -203,6 +203,7 @@ int run_batch_graph(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const c
     a.order = (uint32_t *)ctx->order.p;
     a.L = L;
     a.n = n;
+    a.n_slots = n_slots;
     a.nc = nc;
     a.grid = tun.workgroups;
     a.lds = lds;
@@ -220,6 +221,7 @@ int run_batch_graph(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const c
     put(&key, (uint64_t)L.bytes);
     put(&key, (uint64_t)a.lds);
     put(&key, ctx->n_rep);
+    put(&key, n_slots);
     put(&key, a.grid);
     put(&key, (uint32_t)sweep_factor_slots(sh.max_p));
     put(&key, (uint32_t)a.timing);

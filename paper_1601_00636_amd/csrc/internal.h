@@ -51,7 +51,7 @@ struct ReqDesc {
     uint64_t ulo;          // this launch covers the request's units ulo .. ulo + ucount - 1
     uint64_t ucount;       //   (unit rb * nwin + win: row block rb, column window win)
     uint32_t slot;         // counter slot and survivor tag of the request
-    uint32_t pad;
+    uint32_t flags;        // kReqRegion: per-row columns of region (1.2)
     const RowInfo *rows;   // row info for p at rows[p - rows_p0]
     uint32_t rows_p0;
     uint32_t ip0;          // p0 of the caller's rectangle (survivor indices)
@@ -59,8 +59,14 @@ struct ReqDesc {
     const uint8_t *nfac;   // number of f[] of p at nfac[p - rows_p0]
 };
 
+// The columns of row p are min(cbrt(p / 9), p / 59) <= q <= 59 p (Theorem 1.2)
+// intersected with [q0, q1], and survivors are tagged p * 2^32 + q.  Needs
+// p <= 72796055 so that 59 p < 2^32.
+constexpr uint32_t kReqRegion = 1;
+constexpr uint32_t kRegionMaxP = 72796055u;
+
 struct SurvEntry {
-    uint64_t idx;          // (p - p0) * (q1 - q0 + 1) + (q - q0)
+    uint64_t idx;          // (p - ip0) * (q1 - q0 + 1) + (q - q0); p * 2^32 + q in a region
     uint32_t req;          // slot of the request
     uint32_t pad;
 };

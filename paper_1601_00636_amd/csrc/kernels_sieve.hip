@@ -53,6 +53,19 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Least q >= 1 that region (1.2) allows in row p >= 1: the smaller of the
+// least a with 9 a^3 >= p and of ceil(p / 59).  a <= 256 covers every
+// p <= 9 * 256^3, beyond the largest row a region may hold.
+__device__ __forceinline__ uint32_t region_qmin(uint32_t p) {
+    uint32_t lo = 1, hi = 256;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (9ull * mid * mid * mid >= p) hi = mid; else lo = mid + 1;
+    }
+    const uint32_t b = p / 59 + (p % 59 != 0);
+    return lo < b ? lo : b;
+}
+
 // x mod d for a per-lane divisor d >= 1 (used at segment setup only)
 __device__ __forceinline__ uint32_t mod_var(uint32_t x, uint32_t d) { return x % d; }
 
@@ -92,7 +105,8 @@ __device__ __forceinline__ void deep_window(const SweepParams &P, const QEntry e
             const unsigned long long pos = atomicAdd(P.surv_n, 1ull);
             if (pos < P.surv_cap) {
                 SurvEntry s;
-                s.idx = (uint64_t)(e.p - R.ip0) * width + (q - R.q0);
+                s.idx = (R.flags & kReqRegion) ? ((uint64_t)e.p << 32) | q
+                                               : (uint64_t)(e.p - R.ip0) * width + (q - R.q0);
                 s.req = R.slot;
                 s.pad = 0;
                 P.surv[pos] = s;
@@ -199,6 +213,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
         R.nrb = uni(R.nrb); R.nwin = uni(R.nwin); R.unit0 = uni64(R.unit0);
         R.rows_p0 = uni(R.rows_p0); R.ip0 = uni(R.ip0);
         R.ulo = uni64(R.ulo); R.ucount = uni64(R.ucount); R.slot = uni(R.slot);
+        R.flags = uni(R.flags);
         const uint64_t rend = R.unit0 + R.ucount;
         if (u >= rend) {
             flush(R);
@@ -237,6 +252,11 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
         const uint32_t nfmax = uni(wave_max(nf));
         const uint32_t wheel_lane = wheel_byte + (rinfo.meta & 15) * (kWheel * 8);
         const uint32_t qs = R.q0 + win0 * kWave;
+        // columns of this row inside region (1.2); idle lanes keep none
+        uint32_t rlo = 1, rhi = 0;
+        if (R.flags & kReqRegion) {
+            if (p) { rlo = region_qmin(p); rhi = 59u * p; }
+        }
 
         uint32_t lb[KD + 1], ok[KD + 1];
 #pragma unroll
@@ -283,6 +303,12 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
             if (rem < (uint32_t)kWave) alive &= (1ull << rem) - 1;
             if (qb == 1) {
                 if (p == 1) alive &= ~1ull;   // (1, 1) is coprime but p = q
+            }
+            if (R.flags & kReqRegion) {
+                const uint32_t below = rlo > qb ? rlo - qb : 0;
+                const uint32_t upto = rhi >= qb ? rhi - qb + 1 : 0;
+                alive &= (upto < (uint32_t)kWave ? (1ull << upto) - 1 : ~0ull) &
+                         (below < (uint32_t)kWave ? ~0ull << below : 0ull);
             }
             npairs = __builtin_popcount((uint32_t)alive) + npairs;
             npairs_hi = __builtin_popcount((uint32_t)(alive >> 32)) + npairs_hi;

@@ -154,12 +154,33 @@ struct SieveOut {
     std::vector<SurvEntry> surv;    // all survivors sorted by (request, index), if fetched
     uint64_t n_surv = 0;            // survivors of the whole call
 };
-void shape_reqs(cuboid_ctx *ctx, std::vector<ReqDesc> &reqs, uint32_t slot0, LaunchShape *sh);
+// Results of one sweep over descriptors grouped into counter slots.
+struct CoreOut {
+    uint32_t nc = 0, n_slots = 0;
+    std::vector<uint64_t> counts;   // [n_slots][nc], non-trivial primes ascending
+    std::vector<uint64_t> pairs;    // [n_slots]
+    std::vector<SurvEntry> surv;    // sorted by (slot, idx), when all fit the scratch
+    uint64_t n_surv = 0;
+    uint64_t units = 0;
+    double sweep_ms = 0;
+};
+void shape_reqs(cuboid_ctx *ctx, std::vector<ReqDesc> &reqs, LaunchShape *sh);
+int sieve_core(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid_tuning &tun,
+               std::vector<ReqDesc> &reqs, uint32_t n_slots, uint64_t surv_cap, hipStream_t s,
+               CoreOut *out);
+int prepare_primes(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes, Plan **pl,
+                   cuboid_tuning *tun, DenseSet **ds);
+void record_timing(cuboid_ctx *ctx, hipStream_t s, const CoreOut &co, const DenseSet &ds,
+                   const cuboid_tuning &tun);
+int region_sieve(cuboid_ctx *ctx, uint32_t p0, uint32_t p1, uint32_t band_rows,
+                 const std::vector<uint32_t> &caller_primes, uint64_t *survivors, uint64_t cap,
+                 uint64_t *n_survivors, uint64_t *counts, uint64_t *n_pairs, uint32_t *r_max,
+                 hipStream_t s);
 SweepParams sweep_params(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const ReqDesc *req,
                          uint32_t n_req, uint64_t units, uint64_t surv_cap);
 int run_batch_graph(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid_tuning &tun,
-                    std::vector<ReqDesc> &reqs, uint64_t surv_cap, hipStream_t s,
-                    uint64_t *units_out);
+                    std::vector<ReqDesc> &reqs, uint32_t n_slots, uint64_t surv_cap,
+                    hipStream_t s, uint64_t *units_out);
 void drop_graphs(cuboid_ctx *ctx);
 int sieve_rects(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes,
                 const std::vector<cuboid_request> &rects, uint64_t surv_cap_total,

@@ -1,0 +1,130 @@
+"""Region (1.2) sieve on the GPU: slices against the oracle, the full scan of
+section 6 against the paper's printed result, rows beyond the resident table
+against per-row rectangles.
+"""
+import json
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1601_00636_amd import binding as cb
+from paper_1601_00636_amd import workloads as wl
+from tests.conftest import golden_path
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    h = cb.cuboid_create(0)
+    yield h
+    assert cb.cuboid_destroy(h) == cb.OK
+
+
+def _oracle_band_rmax(p0, p1, band, primes):
+    """r_max per band from the oracle's own region sieve of each band."""
+    asc = sorted(primes)
+    out = []
+    for a in range(p0, p1 + 1, band):
+        b = min(p1, a + band - 1)
+        ref = oracle.sieve_region(a, b, primes)
+        if ref["n_pairs"] == 0:
+            out.append(1)
+        elif ref["n_survivors"]:
+            out.append(asc[-1])
+        else:
+            nz = [asc[i] for i, c in enumerate(ref["counts"]) if c]
+            out.append(max(nz))
+    return out
+
+
+def _check_slice(ctx, p0, p1, primes, band):
+    ref = oracle.sieve_region(p0, p1, primes)
+    got = cb.cuboid_sieve_region(ctx, p0, p1, primes, band_rows=band)
+    asc = sorted(primes)
+    by_prime = dict(zip(asc, [int(c) for c in ref["counts"]]))
+    assert got["n_pairs"] == ref["n_pairs"]
+    assert [int(c) for c in got["counts"]] == [by_prime[r] for r in primes]
+    assert got["n_survivors"] == ref["n_survivors"]
+    assert got["survivors"] == ref["survivors"]
+    assert [int(x) for x in got["r_max"]] == _oracle_band_rmax(p0, p1, band, primes)
+    return got, ref
+
+
+@pytest.mark.parametrize("p0,p1,band", [
+    (1, 151, 100),       # (5.1): q >= p / 59
+    (152, 1151, 100),    # (5.2): q >= cbrt(p / 9), from Start_searching(152, 3)
+    (140, 170, 7),       # across the switch between the two lower bounds
+    (9000, 9040, 13),
+    (40000, 40010, 4),
+])
+def test_region_slices_against_oracle(ctx, p0, p1, band):
+    got, ref = _check_slice(ctx, p0, p1, wl.PRIMES_PAPER, band)
+    assert got["n_survivors"] == 0
+    depth_prime = wl.PRIMES_PAPER[ref["max_depth"] - 1]
+    assert max(int(x) for x in got["r_max"]) == depth_prime
+
+
+def test_region_survivors_small_primes(ctx):
+    # few primes: survivors exist and come back as ascending (p, q)
+    primes = [31, 13, 3, 11, 7, 17, 19, 29, 23, 5]
+    got, ref = _check_slice(ctx, 1, 300, primes, 50)
+    assert got["n_survivors"] > 10
+    assert got["survivors"] == sorted(got["survivors"])
+    assert max(int(x) for x in got["r_max"]) == 31
+
+
+def test_region_matches_rectangles_rowwise_beyond_resident_rows(ctx):
+    # rows above 2^24 use row windows computed on the fly; each row of the
+    # region equals the rectangle [p, p] x [qmin(p), 59 p]
+    p0, p1 = 16777213, 16777218
+    primes = wl.PRIMES_C2
+    got = cb.cuboid_sieve_region(ctx, p0, p1, primes, band_rows=1)
+    tot_pairs, tot, surv, rmax = 0, np.zeros(len(primes), dtype=np.int64), [], []
+    for p in range(p0, p1 + 1):
+        qlo = oracle.region_qmin(p)
+        r = cb.cuboid_sieve_range(ctx, p, p, qlo, 59 * p, primes, cap=1 << 12)
+        tot_pairs += r["n_pairs"]
+        tot += r["counts"].astype(np.int64)
+        surv += [(p, qlo + int(i)) for i in r["survivors"]]
+        nz = [rp for rp, c in zip(primes, r["counts"]) if c]
+        rmax.append(max(primes) if r["n_survivors"] else max(nz))
+    assert got["n_pairs"] == tot_pairs
+    assert [int(c) for c in got["counts"]] == tot.tolist()
+    assert got["survivors"] == surv
+    assert [int(x) for x in got["r_max"]] == rmax
+
+
+def test_region_errors(ctx):
+    for args, code in (((0, 5), cb.E_RANGE), ((6, 5), cb.E_RANGE),
+                       ((1, 72796056), cb.E_LIMIT)):
+        with pytest.raises(cb.CuboidError) as e:
+            cb.cuboid_sieve_region(ctx, *args, wl.PRIMES_PAPER)
+        assert e.value.status == code
+    with pytest.raises(cb.CuboidError) as e:
+        cb.cuboid_sieve_region(ctx, 1, 10, wl.PRIMES_PAPER, band_rows=0)
+    assert e.value.status == cb.E_ARG
+    with pytest.raises(cb.CuboidError) as e:
+        cb.cuboid_sieve_region(ctx, 1, 300, [11, 13, 17], cap=2)
+    assert e.value.status == cb.E_CAPACITY and e.value.needed > 2
+
+
+def test_section6_scan_matches_the_paper(ctx):
+    """p = 1..154000 over region (1.2) with the 96 primes 11..541: the paper
+    reports that no pair passes the sieve and that the deepest prime reached is
+    the 29th, 137 (section 6)."""
+    with open(golden_path("paper_constants.json")) as f:
+        pc = json.load(f)
+    md = pc["max_depth"]
+    primes = wl.PRIMES_PAPER
+    assert len(primes) == pc["sieve_primes"]["count"]
+    got = cb.cuboid_sieve_region(ctx, 1, md["p_max"], primes, band_rows=100)
+    print("section 6 scan: %d coprime pairs, %d survivors, deepest prime %d"
+          % (got["n_pairs"], got["n_survivors"], int(got["r_max"].max())), flush=True)
+    assert got["n_survivors"] == 0
+    assert int(got["r_max"].max()) == md["prime"] == primes[md["index"] - 1]
+    assert len(got["r_max"]) == md["p_max"] // 100
+    assert sum(int(c) for c in got["counts"]) == got["n_pairs"]
+    # the scanned pairs are a coprime subset of the ~0.7e12 the paper counts
+    assert 0.55 * pc["pairs_tested"]["value"] < got["n_pairs"] < pc["pairs_tested"]["value"]
