@@ -48,6 +48,14 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
     return v;
 }
 
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        uint32_t w = __shfl_xor(v, o, kWave);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -252,11 +260,21 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
         const uint32_t nfmax = uni(wave_max(nf));
         const uint32_t wheel_lane = wheel_byte + (rinfo.meta & 15) * (kWheel * 8);
         const uint32_t qs = R.q0 + win0 * kWave;
-        // columns of this row inside region (1.2); idle lanes keep none
-        uint32_t rlo = 1, rhi = 0;
-        if (R.flags & kReqRegion) {
-            if (p) { rlo = region_qmin(p); rhi = 59u * p; }
+        // columns of this lane's row: [q0, q1], cut to region (1.2) in a
+        // region; only windows reaching past the wave's tightest bounds need
+        // per-lane masks (idle lanes keep the request's bounds: their wheel
+        // row already clears every column)
+        uint32_t rlo = R.q0, rhi = R.q1;
+        if ((R.flags & kReqRegion) && p) {
+            const uint32_t a = region_qmin(p), b = 59u * p;
+            rlo = a > rlo ? a : rlo;
+            rhi = b < rhi ? b : rhi;
         }
+        if (p == 1 && rlo < 2) rlo = 2;   // (1, 1) is coprime but p = q
+        const uint32_t lo_max = uni(wave_max(rlo));
+        const uint32_t hi_min = uni(wave_min(rhi));
+        // a window starting above edge_hi reaches past hi_min
+        const uint32_t edge_hi = hi_min >= (uint32_t)(kWave - 1) ? hi_min - (kWave - 1) : 0;
 
         uint32_t lb[KD + 1], ok[KD + 1];
 #pragma unroll
@@ -299,12 +317,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
                 }
             }
             uint64_t alive = ~nc;
-            const uint32_t rem = R.q1 - qb + 1;
-            if (rem < (uint32_t)kWave) alive &= (1ull << rem) - 1;
-            if (qb == 1) {
-                if (p == 1) alive &= ~1ull;   // (1, 1) is coprime but p = q
-            }
-            if (R.flags & kReqRegion) {
+            if (qb < lo_max || qb > edge_hi) {
                 const uint32_t below = rlo > qb ? rlo - qb : 0;
                 const uint32_t upto = rhi >= qb ? rhi - qb + 1 : 0;
                 alive &= (upto < (uint32_t)kWave ? (1ull << upto) - 1 : ~0ull) &

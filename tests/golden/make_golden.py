@@ -6,8 +6,10 @@ Workloads (sieve over all coprime p != q in the square, primes as listed):
   c2  1 <= p, q <= 10^4,   primes 3..97
   c3  1 <= p, q <= 10^5,   primes 3..997
   c4s a seeded sample of the batched workload's rectangles, primes 3..499
+  s6  region (1.2) for p = 1..154000, primes 11..541 (the scan of section 6),
+      per hundred of p: the deepest prime some pair was tested against
 
-usage: python tests/golden/make_golden.py [c1 c2 c3 c4s]
+usage: python tests/golden/make_golden.py [c1 c2 c3 c4s s6]
 """
 import json
 import os
@@ -74,10 +76,43 @@ def c4_sample():
     print("c4s", len(picks), "requests", out["oracle_seconds"], "s")
 
 
+def section6(p_max=154000, band=100):
+    primes = primes_in(11, 541)
+    for r in primes:
+        oracle.table(r)
+    counts = [0] * len(primes)
+    pairs = surv = 0
+    r_max = []
+    t = time.time()
+    for a in range(1, p_max + 1, band):
+        b = min(p_max, a + band - 1)
+        res = oracle.sieve_region(a, b, primes)
+        pairs += int(res["n_pairs"])
+        surv += int(res["n_survivors"])
+        cs = [int(c) for c in res["counts"]]
+        counts = [x + y for x, y in zip(counts, cs)]
+        if res["n_pairs"] == 0:
+            r_max.append(1)
+        elif res["n_survivors"]:
+            r_max.append(primes[-1])
+        else:
+            r_max.append(max(r for r, c in zip(primes, cs) if c))
+        if a % 10000 == 1:
+            print("s6 p <= %d: %.0f s" % (b, time.time() - t), flush=True)
+    out = dict(workload="s6", p0=1, p1=p_max, band_rows=band, primes=primes, counts=counts,
+               n_pairs=pairs, n_survivors=surv, r_max=r_max, max_depth_prime=max(r_max),
+               oracle_seconds=round(time.time() - t, 1))
+    with open(os.path.join(HERE, "oracle_s6.json"), "w") as f:
+        json.dump(out, f)
+    print("s6 pairs", pairs, "survivors", surv, "depth", max(r_max), out["oracle_seconds"], "s")
+
+
 if __name__ == "__main__":
     names = sys.argv[1:] or ["c1", "c2", "c3", "c4s"]
     for nm in names:
         if nm == "c4s":
             c4_sample()
+        elif nm == "s6":
+            section6()
         else:
             square(nm)
