@@ -175,8 +175,12 @@ def main():
 
     req_arr = np.asarray(reqs, dtype=np.int64)
 
+    req_u32 = np.ascontiguousarray(req_arr, dtype=np.uint32)
+    held = [None]   # result arrays reused from step to step, as a serving loop would
+
     def step():
-        st, out = cb.cuboid_sieve_batch(ctx, req_arr, primes, caps=256, stream=stream)
+        st, out = cb.cuboid_sieve_batch(ctx, req_u32, primes, caps=256, stream=stream, out=held[0])
+        held[0] = out
         if st != cb.OK:
             raise RuntimeError("batch status %d" % st)
         sweep = cb.cuboid_last_timing(ctx)
@@ -285,6 +289,26 @@ def main():
                                       "ms": float(np.median(reps)) * 1e3,
                                       "sweep_ms": t3["sweep_ms"], "n_pairs": r3["n_pairs"],
                                       "sweep_pairs_per_s": r3["n_pairs"] / (t3["sweep_ms"] * 1e-3)}
+
+    if not args.no_extras:
+        # the scan of the paper's section 6: region (1.2), p = 1..154000,
+        # primes 11..541, progress reported per hundred of p
+        pp = wl.PRIMES_PAPER
+        cb.cuboid_sieve_region(ctx, 1, 154000, pp, band_rows=100, stream=stream)
+        reps = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            g6 = cb.cuboid_sieve_region(ctx, 1, 154000, pp, band_rows=100, stream=stream)
+            torch.cuda.synchronize()
+            reps.append(time.perf_counter() - t0)
+        t6 = cb.cuboid_last_timing(ctx)
+        dt = float(np.median(reps))
+        res["extras"]["section6_scan"] = {
+            "p_range": [1, 154000], "primes": "11..541 (96)", "band_rows": 100,
+            "coprime_pairs": g6["n_pairs"], "survivors": g6["n_survivors"],
+            "deepest_prime": int(g6["r_max"].max()), "ms": dt * 1e3, "sweep_ms": t6["sweep_ms"],
+            "value": g6["n_pairs"] / dt,
+            "paper_hours": 4130 / 60.0}
 
     if not args.no_extras and args.served_seconds > 0:
         res["extras"]["served"] = run_served(cb, wl, ctx, primes, args.served_seconds)

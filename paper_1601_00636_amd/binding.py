@@ -266,6 +266,15 @@ class BatchResult:
         self.status, self.counts, self.n_pairs = status, counts, n_pairs
         self.n_survivors, self.survivors_flat, self.offsets = n_survivors, flat, offsets
 
+    _res = None
+    _caps = None
+
+    def fits(self, n, n_primes, caps):
+        """Whether a call with n requests, n_primes primes and these caps can
+        reuse this result's arrays."""
+        return (self._res is not None and len(self.status) == n and self.counts.shape[1] == n_primes
+                and np.array_equal(self._caps, caps))
+
     def __len__(self):
         return len(self.status)
 
@@ -283,27 +292,37 @@ class BatchResult:
         return (self[i] for i in range(len(self)))
 
 
-def cuboid_sieve_batch(ctx, requests, primes, caps=1024, stream=None):
-    """requests: (n, 4) array-like of (p0, p1, q0, q1).  Returns (status, BatchResult)."""
+def cuboid_sieve_batch(ctx, requests, primes, caps=1024, stream=None, out=None):
+    """requests: (n, 4) array-like of (p0, p1, q0, q1).  Returns (status, BatchResult).
+
+    out: a BatchResult of an earlier call with the same number of requests,
+    primes and caps; its arrays are overwritten instead of allocating new ones."""
     pr = _arr(primes, np.uint32)
     reqa = np.ascontiguousarray(np.asarray(requests, dtype=np.uint32).reshape(-1, 4))
     n = reqa.shape[0]
     caps = np.full(n, caps, dtype=np.uint64) if np.isscalar(caps) else _arr(caps, np.uint64)
-    offsets = np.zeros(n + 1, dtype=np.uint64)
-    np.cumsum(caps, out=offsets[1:])
-    flat = np.zeros(max(1, int(offsets[-1])), dtype=np.uint64)
-    counts = np.zeros((n, max(1, len(pr))), dtype=np.uint64)
-    res = np.zeros(max(1, n), dtype=_RESULT_DTYPE)
-    res["survivors"][:n] = flat.ctypes.data + offsets[:-1] * 8
-    res["cap"][:n] = caps
-    res["counts"][:n] = counts.ctypes.data + np.arange(n, dtype=np.uint64) * (counts.shape[1] * 8)
+    if out is not None and out.fits(n, len(pr), caps):
+        res, counts, flat, offsets = out._res, out.counts, out.survivors_flat, out.offsets
+    else:
+        offsets = np.zeros(n + 1, dtype=np.uint64)
+        np.cumsum(caps, out=offsets[1:])
+        flat = np.empty(max(1, int(offsets[-1])), dtype=np.uint64)
+        counts = np.zeros((n, max(1, len(pr))), dtype=np.uint64)[:, :len(pr)]
+        res = np.zeros(max(1, n), dtype=_RESULT_DTYPE)
+        res["survivors"][:n] = flat.ctypes.data + offsets[:-1] * 8
+        res["cap"][:n] = caps
+        res["counts"][:n] = counts.ctypes.data + np.arange(n, dtype=np.uint64) * (counts.strides[0])
     st = _load().cuboid_sieve_batch(ctx, reqa.ctypes.data_as(P(cuboid_request)), n, _p(pr, u32),
                                     len(pr), res.ctypes.data_as(P(cuboid_result)),
                                     _stream(stream))
     if st not in (OK, E_CAPACITY, E_LIMIT):
         _check(st, "cuboid_sieve_batch")
-    return st, BatchResult(res["status"][:n].copy(), counts[:, :len(pr)], res["n_pairs"][:n].copy(),
-                           res["n_survivors"][:n].copy(), flat, offsets)
+    if out is not None and out._res is res:
+        return st, out
+    r = BatchResult(res["status"][:n], counts, res["n_pairs"][:n], res["n_survivors"][:n], flat,
+                    offsets)
+    r._res, r._caps = res, caps.copy()
+    return st, r
 
 
 def cuboid_enable_timing(ctx, on=True):

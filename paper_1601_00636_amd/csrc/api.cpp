@@ -195,11 +195,11 @@ int cuboid_sieve_range(cuboid_ctx *ctx, uint32_t p0, uint32_t p1, uint32_t q0, u
     std::lock_guard<std::recursive_mutex> g(ctx->mu);
     if (set_device(ctx)) return CUBOID_E_DEVICE;
     const std::vector<uint32_t> caller(primes, primes + n_primes);
-    std::vector<cuboid_request> rects(1);
-    rects[0].p0 = p0; rects[0].p1 = p1; rects[0].q0 = q0; rects[0].q1 = q1;
-    SieveOut so;
+    cuboid_request rect;
+    rect.p0 = p0; rect.p1 = p1; rect.q0 = q0; rect.q1 = q1;
+    SieveOut &so = ctx->h_out;
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
-    st = sieve_rects(ctx, caller, rects, cap, s, &so);
+    st = sieve_rects(ctx, caller, &rect, 1, cap, s, &so);
     if (st) return st;
     memcpy(counts, so.counts.data(), n_primes * 8);
     *n_pairs = so.pairs[0];
@@ -249,17 +249,16 @@ int cuboid_sieve_batch(cuboid_ctx *ctx, const cuboid_request *req, uint32_t n_re
     std::lock_guard<std::recursive_mutex> g(ctx->mu);
     if (set_device(ctx)) return CUBOID_E_DEVICE;
     const std::vector<uint32_t> caller(primes, primes + n_primes);
-    const std::vector<cuboid_request> rects(req, req + n_req);
-    SieveOut so;
+    SieveOut &so = ctx->h_out;
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
     // a request may hold more survivors than its own cap while the total fits;
     // the device list holds up to the sum of the caps
-    st = sieve_rects(ctx, caller, rects, cap_total, s, &so);
+    st = sieve_rects(ctx, caller, req, n_req, cap_total, s, &so);
     if (st && st != CUBOID_E_LIMIT) return st;
     if (st == CUBOID_OK && so.n_surv > cap_total && so.n_surv <= kMaxSurvScratch) {
         // some request holds more survivors than its cap: run again with room
         // for all of them so every other request still gets its full list
-        st = sieve_rects(ctx, caller, rects, so.n_surv, s, &so);
+        st = sieve_rects(ctx, caller, req, n_req, so.n_surv, s, &so);
         if (st && st != CUBOID_E_LIMIT) return st;
     }
     for (uint32_t i = 0; i < n_req; ++i) {

@@ -110,8 +110,8 @@ extern "C" int cuboid_autotune(cuboid_ctx *ctx, const uint32_t *primes, uint32_t
             ctx->tunings[sorted] = t;
             double ms_best = 1e30;
             for (int rep = 0; rep < 3; ++rep) {
-                SieveOut so;
-                st = sieve_rects(ctx, sorted, rect, 1 << 16, ctx->stream, &so);
+                st = sieve_rects(ctx, sorted, rect.data(), (uint32_t)rect.size(), 1 << 16,
+                                 ctx->stream, &ctx->h_out);
                 if (st) break;
                 ms_best = std::min(ms_best, ctx->last.sweep_ms);
             }

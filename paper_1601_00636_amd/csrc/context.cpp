@@ -352,7 +352,7 @@ int launch_reqs(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboi
                 std::vector<ReqDesc> &reqs, uint64_t surv_cap, hipStream_t s,
                 uint64_t *units_out) {
     const uint32_t n = (uint32_t)reqs.size();
-    LaunchShape sh;
+    LaunchShape &sh = ctx->h_shape;
     shape_reqs(ctx, reqs, &sh);
     if (sh.n_order) HIPCHK(ctx->order.ensure(sh.n_order * 4));
     set_order(reqs, sh, (uint32_t *)ctx->order.p);
@@ -593,16 +593,16 @@ void record_timing(cuboid_ctx *ctx, hipStream_t s, const CoreOut &co, const Dens
 
 // The plain and batched sieve share this path.  `rects` are validated.
 int sieve_rects(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes,
-                const std::vector<cuboid_request> &rects, uint64_t surv_cap_total,
+                const cuboid_request *rects, uint32_t n_req, uint64_t surv_cap_total,
                 hipStream_t s, SieveOut *out) {
     Plan *pl = nullptr;
     DenseSet *ds = nullptr;
     cuboid_tuning tun;
     int st = prepare_primes(ctx, caller_primes, &pl, &tun, &ds);
     if (st) return st;
-    const uint32_t n_req = (uint32_t)rects.size();
     const uint64_t surv_cap = std::min<uint64_t>(surv_cap_total, kMaxSurvScratch);
-    std::vector<ReqDesc> reqs(n_req);
+    std::vector<ReqDesc> &reqs = ctx->h_reqs;
+    reqs.resize(n_req);
     for (uint32_t i = 0; i < n_req; ++i) {
         ReqDesc &d = reqs[i];
         memset(&d, 0, sizeof(d));
@@ -611,7 +611,7 @@ int sieve_rects(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes,
         d.slot = i;
     }
     if (ctx->timing) HIPCHK(hipEventRecord(ctx->ev_total0, s));
-    CoreOut co;
+    CoreOut &co = ctx->h_core;
     st = sieve_core(ctx, *pl, *ds, tun, reqs, n_req, surv_cap, s, &co);
     if (st) return st;
     const uint32_t nc = co.nc;
@@ -626,8 +626,8 @@ int sieve_rects(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes,
         uint64_t *o = out->counts.data() + (size_t)i * np;
         for (uint32_t j = 0; j < np; ++j) o[j] = col[j] < 0 ? 0 : c[col[j]];
     }
-    out->pairs = std::move(co.pairs);
-    out->surv = std::move(co.surv);
+    out->pairs.assign(co.pairs.begin(), co.pairs.end());
+    out->surv.assign(co.surv.begin(), co.surv.end());
     record_timing(ctx, s, co, *ds, tun);
     if (co.n_surv > surv_cap && surv_cap < surv_cap_total) return CUBOID_E_LIMIT;
     return CUBOID_OK;

@@ -168,7 +168,7 @@ int run_batch_graph(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const c
                     hipStream_t s, uint64_t *units_out) {
     const uint32_t n = (uint32_t)reqs.size();
     const uint32_t nc = ds.K + ds.n_deep;
-    LaunchShape sh;
+    LaunchShape &sh = ctx->h_shape;
     shape_reqs(ctx, reqs, &sh);
     if (sh.n_order) {
         // room to spare so later batches keep the same buffer (and graph)

@@ -67,7 +67,8 @@ int region_sieve(cuboid_ctx *ctx, uint32_t p0, uint32_t p1, uint32_t band_rows,
     if (ctx->timing && hipEventRecord(ctx->ev_total0, s) != hipSuccess) return CUBOID_E_DEVICE;
     for (uint64_t b0 = 0; b0 < n_bands; b0 += kSlotsPerCall) {
         const uint32_t nb = (uint32_t)std::min<uint64_t>(kSlotsPerCall, n_bands - b0);
-        std::vector<ReqDesc> reqs;
+        std::vector<ReqDesc> &reqs = ctx->h_reqs;
+        reqs.clear();
         for (uint32_t j = 0; j < nb; ++j) {
             const uint64_t ba = p0 + (b0 + j) * band_rows;
             const uint64_t bb = std::min<uint64_t>(p1, ba + band_rows - 1);
@@ -86,7 +87,7 @@ int region_sieve(cuboid_ctx *ctx, uint32_t p0, uint32_t p1, uint32_t band_rows,
                 a = e + 1;
             }
         }
-        CoreOut co;
+        CoreOut &co = ctx->h_core;
         st = sieve_core(ctx, *pl, *ds, tun, reqs, nb, surv_cap, s, &co);
         if (st) return st;
         sum.units += co.units;

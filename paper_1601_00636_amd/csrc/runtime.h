@@ -85,6 +85,25 @@ struct BatchGraph {
     uint64_t last_use = 0;
 };
 
+// Results of one sweep over descriptors grouped into counter slots.
+struct CoreOut {
+    uint32_t nc = 0, n_slots = 0;
+    std::vector<uint64_t> counts;   // [n_slots][nc], non-trivial primes ascending
+    std::vector<uint64_t> pairs;    // [n_slots]
+    std::vector<SurvEntry> surv;    // sorted by (slot, idx), when all fit the scratch
+    uint64_t n_surv = 0;
+    uint64_t units = 0;
+    double sweep_ms = 0;
+};
+// Results of one sieve call over several rectangles.
+struct SieveOut {
+    uint32_t n_req = 0, n_primes = 0;
+    std::vector<uint64_t> counts;   // [n_req][n_primes], caller's prime order
+    std::vector<uint64_t> pairs;    // [n_req]
+    std::vector<SurvEntry> surv;    // all survivors sorted by (request, index), if fetched
+    uint64_t n_surv = 0;            // survivors of the whole call
+};
+
 }  // namespace cuboid
 
 struct cuboid_ctx {
@@ -118,6 +137,13 @@ struct cuboid_ctx {
     bool bucketing = true;
     cuboid::HostBuf req_stage, result_stage;
 
+    // host scratch reused from call to call (no per-call allocation, so no
+    // page faults on fresh heap memory inside the timed path)
+    std::vector<cuboid::ReqDesc> h_reqs;
+    cuboid::LaunchShape h_shape;
+    cuboid::CoreOut h_core;
+    cuboid::SieveOut h_out;
+
     // captured batch launches
     bool use_graphs = true;
     std::vector<cuboid::BatchGraph> graphs;
@@ -146,24 +172,6 @@ int ensure_rows_serving(cuboid_ctx *ctx, uint32_t p_max);   // by a drained serv
 std::vector<int32_t> count_columns(const Plan &pl, const std::vector<uint32_t> &caller);
 cuboid_tuning tuning_for(cuboid_ctx *ctx, const std::vector<uint32_t> &primes, const Plan &pl);
 int rect_valid(uint32_t p0, uint32_t p1, uint32_t q0, uint32_t q1);
-// Results of one sieve call over several rectangles.
-struct SieveOut {
-    uint32_t n_req = 0, n_primes = 0;
-    std::vector<uint64_t> counts;   // [n_req][n_primes], caller's prime order
-    std::vector<uint64_t> pairs;    // [n_req]
-    std::vector<SurvEntry> surv;    // all survivors sorted by (request, index), if fetched
-    uint64_t n_surv = 0;            // survivors of the whole call
-};
-// Results of one sweep over descriptors grouped into counter slots.
-struct CoreOut {
-    uint32_t nc = 0, n_slots = 0;
-    std::vector<uint64_t> counts;   // [n_slots][nc], non-trivial primes ascending
-    std::vector<uint64_t> pairs;    // [n_slots]
-    std::vector<SurvEntry> surv;    // sorted by (slot, idx), when all fit the scratch
-    uint64_t n_surv = 0;
-    uint64_t units = 0;
-    double sweep_ms = 0;
-};
 void shape_reqs(cuboid_ctx *ctx, std::vector<ReqDesc> &reqs, LaunchShape *sh);
 int sieve_core(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid_tuning &tun,
                std::vector<ReqDesc> &reqs, uint32_t n_slots, uint64_t surv_cap, hipStream_t s,
@@ -183,7 +191,7 @@ int run_batch_graph(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const c
                     hipStream_t s, uint64_t *units_out);
 void drop_graphs(cuboid_ctx *ctx);
 int sieve_rects(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes,
-                const std::vector<cuboid_request> &rects, uint64_t surv_cap_total,
+                const cuboid_request *rects, uint32_t n_req, uint64_t surv_cap_total,
                 hipStream_t s, SieveOut *out);
 
 }  // namespace cuboid

@@ -140,3 +140,18 @@ def test_graphs_off_and_on_again(pair):
     finally:
         cb.cuboid_enable_graphs(g, True)
     _cmp(cb.cuboid_sieve_range(g, *rect, wl.PRIMES_C1), ref)
+
+
+def test_result_arrays_reused_across_calls(pair):
+    g, e = pair
+    primes = wl.PRIMES_C1
+    held = None
+    for seed in range(3):
+        rects = wl.random_rectangles(50, seed=300 + seed, max_coord=3000, max_side=300)
+        st, held_new = cb.cuboid_sieve_batch(g, rects, primes, caps=128, out=held)
+        if held is not None:
+            assert held_new is held          # same arrays, overwritten
+        held = held_new
+        st_e, fresh = cb.cuboid_sieve_batch(e, rects, primes, caps=128)
+        assert st == st_e
+        _same_batch(held, fresh)
