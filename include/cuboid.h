@@ -322,6 +322,58 @@ int cuboid_set_tuning(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes
 int cuboid_get_tuning(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes,
                       cuboid_tuning *out);
 
+/* ------------------------------------------------------------------ search */
+
+/*
+ * Resumable background search over region (1.2), after the search loop of
+ * section 5 (Start_searching, Get_current_p, Get_current_r_max,
+ * Stop_searching).  A host thread scans, from row p and column q on, every
+ * row p' <= p_end with the columns of (5.2), min(cbrt(p'/9), p'/59) <= q' <=
+ * 59 p', through the same sieve as cuboid_sieve_region.
+ */
+typedef struct cuboid_search cuboid_search;   /* opaque, owned by the library */
+
+typedef struct cuboid_search_report {
+    uint32_t p, q;          /* next pair to scan (row p from column q); after a */
+                            /* stop, the exit point to restart from             */
+    uint32_t p_hundred;     /* p rounded down to a multiple of 100 (the paper's */
+                            /* Get_current_p)                                   */
+    uint32_t r_max;         /* largest prime used in the last hundred of p      */
+                            /* scanned; 1 again at each new hundred             */
+    uint64_t pairs;         /* coprime pairs scanned since the start            */
+    uint64_t survivors;     /* pairs no prime rejected since the start          */
+    int64_t unix_time;      /* when this report was taken, seconds              */
+    int32_t running;        /* 1 while the search thread runs                   */
+    int32_t status;         /* CUBOID_OK, or the error that ended the search    */
+} cuboid_search_report;
+
+/*
+ * Starts the search thread and returns at once (section 5: Start_searching,
+ * whose first call is Start_searching(152, 3)).  p_end = 0 means up to
+ * 72796055, the last p with 59 p < 2^32.  report_path (may be NULL) names a
+ * text file that cuboid_search_stop appends its report line to.  One search
+ * per context at a time; the context cannot be destroyed while it runs.
+ * Errors: E_BUSY (a search is running on ctx), E_RANGE (p < 152, q outside
+ * (5.2) for row p, or p_end < p), E_LIMIT (p > 72796055), E_PRIMES,
+ * E_NOT_LOADED, E_ARG.
+ */
+int cuboid_search_start(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes, uint32_t p,
+                        uint32_t q, uint32_t p_end, const char *report_path,
+                        cuboid_search **out);
+/* Progress (section 5: Get_current_p, Get_current_r_max), any time. */
+int cuboid_search_current(cuboid_search *s, cuboid_search_report *out);
+/* Pairs that passed every prime so far, as ascending p * 2^32 + q (the first
+ * 2^20 kept); *n gets their number; E_CAPACITY if cap is smaller. */
+int cuboid_search_survivors(cuboid_search *s, uint64_t *pq, uint64_t cap, uint64_t *n);
+/*
+ * Stops at the next row boundary (or takes the finished search), writes the
+ * final report to *out (may be NULL), appends to the report file the time
+ * stamp line and "Stop with p=<p>, q=<q>, r_max=<r_max>" (section 5), frees
+ * the search and returns its status.  Restarting from report.p, report.q
+ * continues without gap or overlap.
+ */
+int cuboid_search_stop(cuboid_search *s, cuboid_search_report *out);
+
 /* ------------------------------------------------------------------ timing */
 
 typedef struct cuboid_timing {

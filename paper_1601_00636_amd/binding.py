@@ -41,6 +41,16 @@ class cuboid_timing(ctypes.Structure):
                 ("dense_primes", u32), ("workgroups", u32), ("graph", u32), ("reserved", u32)]
 
 
+class cuboid_search_report(ctypes.Structure):
+    _fields_ = [("p", u32), ("q", u32), ("p_hundred", u32), ("r_max", u32), ("pairs", u64),
+                ("survivors", u64), ("unix_time", ctypes.c_int64), ("running", i32),
+                ("status", i32)]
+
+
+def _report(r):
+    return {k: getattr(r, k) for k, _ in cuboid_search_report._fields_}
+
+
 class cuboid_server_config(ctypes.Structure):
     _fields_ = [("streams", u32), ("max_slots", u32), ("max_launch_units", u64),
                 ("hbm_budget_bytes", u64)]
@@ -96,6 +106,10 @@ def _load():
         "cuboid_enable_timing": ([vp, i32], i32),
         "cuboid_last_timing": ([vp, P(cuboid_timing)], i32),
         "cuboid_enable_graphs": ([vp, i32], i32),
+        "cuboid_search_start": ([vp, P(u32), u32, u32, u32, u32, ctypes.c_char_p, P(vp)], i32),
+        "cuboid_search_current": ([vp, P(cuboid_search_report)], i32),
+        "cuboid_search_survivors": ([vp, P(u64), u64, P(u64)], i32),
+        "cuboid_search_stop": ([vp, P(cuboid_search_report)], i32),
         "cuboid_server_start": ([vp, P(u32), u32, P(cuboid_server_config), P(vp)], i32),
         "cuboid_server_submit": ([vp, P(cuboid_request), P(u64)], i32),
         "cuboid_server_poll": ([vp, u64, P(cuboid_result), i32, P(cuboid_request_timing)], i32),
@@ -215,6 +229,39 @@ def cuboid_sieve_region(ctx, p0, p1, primes, band_rows=100, cap=1 << 16, stream=
     return dict(counts=counts[:len(pr)], n_pairs=npairs.value, n_survivors=ns.value,
                 survivors=[(int(x >> np.uint64(32)), int(x & np.uint64(0xffffffff))) for x in sv],
                 r_max=rmax[:n_bands].copy())
+
+
+def cuboid_search_start(ctx, primes, p=152, q=3, p_end=0, report_path=None):
+    """Starts the background region search; returns its handle."""
+    pr = _arr(primes, np.uint32)
+    h = ctypes.c_void_p()
+    rp = report_path.encode() if report_path else None
+    _check(_load().cuboid_search_start(ctx, _p(pr, u32), len(pr), int(p), int(q), int(p_end), rp,
+                                       ctypes.byref(h)), "cuboid_search_start")
+    return h
+
+
+def cuboid_search_current(h):
+    r = cuboid_search_report()
+    _check(_load().cuboid_search_current(h, ctypes.byref(r)), "cuboid_search_current")
+    return _report(r)
+
+
+def cuboid_search_survivors(h, cap=1 << 16):
+    buf = np.zeros(max(1, cap), dtype=np.uint64)
+    n = ctypes.c_uint64(0)
+    st = _load().cuboid_search_survivors(h, _p(buf, u64), int(cap), ctypes.byref(n))
+    _check(st, "cuboid_search_survivors", needed=n.value if st == E_CAPACITY else None)
+    return [(int(x >> np.uint64(32)), int(x & np.uint64(0xffffffff))) for x in buf[:n.value]]
+
+
+def cuboid_search_stop(h):
+    """Stops the search; returns its final report (raises if it ended in error)."""
+    r = cuboid_search_report()
+    st = _load().cuboid_search_stop(h, ctypes.byref(r))
+    rep = _report(r)
+    _check(st, "cuboid_search_stop")
+    return rep
 
 
 def cuboid_root_check(ctx, p, q, cap=1 << 16):

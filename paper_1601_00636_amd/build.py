@@ -21,6 +21,7 @@ SOURCES = [
     "bigint.cpp",
     "graph.cpp",
     "region.cpp",
+    "search.cpp",
     "context.cpp",
     "autotune.cpp",
     "server.cpp",

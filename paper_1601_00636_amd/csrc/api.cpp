@@ -124,7 +124,7 @@ int cuboid_create(cuboid_ctx **out, int hip_device) {
 
 int cuboid_destroy(cuboid_ctx *ctx) {
     if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
-    if (ctx->servers.load() > 0) return CUBOID_E_BUSY;
+    if (ctx->servers.load() > 0 || ctx->searches.load() > 0) return CUBOID_E_BUSY;
     if (!ctx->mu.try_lock()) return CUBOID_E_BUSY;
     {
         std::lock_guard<std::mutex> g(g_ctx_mu);
@@ -142,7 +142,7 @@ int cuboid_q_mod_prime(cuboid_ctx *ctx, const uint32_t *p, const uint32_t *q, co
     if (!p || !q || !t || !r || !out) return CUBOID_E_ARG;
     for (uint64_t i = 0; i < n; ++i)
         if (r[i] < 2 || r[i] >= 65536) return CUBOID_E_ARG;
-    std::lock_guard<std::recursive_mutex> g(ctx->mu);
+    CtxLock g(ctx);
     if (set_device(ctx)) return CUBOID_E_DEVICE;
     DevBuf d;
     HIPCHK(d.ensure(n * 4 * 5));
@@ -166,7 +166,7 @@ int cuboid_table_bytes(cuboid_ctx *ctx, uint32_t r, uint8_t *out, size_t cap, si
     *written = nbytes;
     if (cap < nbytes) return CUBOID_E_CAPACITY;
     if (!out) return CUBOID_E_ARG;
-    std::lock_guard<std::recursive_mutex> g(ctx->mu);
+    CtxLock g(ctx);
     if (set_device(ctx)) return CUBOID_E_DEVICE;
     Plan *pl = nullptr;
     const std::vector<uint32_t> one(1, r);
@@ -192,7 +192,7 @@ int cuboid_sieve_range(cuboid_ctx *ctx, uint32_t p0, uint32_t p1, uint32_t q0, u
     std::vector<uint32_t> sorted;
     st = canonical_primes(primes, n_primes, &sorted);
     if (st) return st;
-    std::lock_guard<std::recursive_mutex> g(ctx->mu);
+    CtxLock g(ctx);
     if (set_device(ctx)) return CUBOID_E_DEVICE;
     const std::vector<uint32_t> caller(primes, primes + n_primes);
     cuboid_request rect;
@@ -221,7 +221,7 @@ int cuboid_sieve_region(cuboid_ctx *ctx, uint32_t p0, uint32_t p1, uint32_t band
     std::vector<uint32_t> sorted;
     int st = canonical_primes(primes, n_primes, &sorted);
     if (st) return st;
-    std::lock_guard<std::recursive_mutex> g(ctx->mu);
+    CtxLock g(ctx);
     if (set_device(ctx)) return CUBOID_E_DEVICE;
     const std::vector<uint32_t> caller(primes, primes + n_primes);
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
@@ -246,7 +246,7 @@ int cuboid_sieve_batch(cuboid_ctx *ctx, const cuboid_request *req, uint32_t n_re
     std::vector<uint32_t> sorted;
     int st = canonical_primes(primes, n_primes, &sorted);
     if (st) return st;
-    std::lock_guard<std::recursive_mutex> g(ctx->mu);
+    CtxLock g(ctx);
     if (set_device(ctx)) return CUBOID_E_DEVICE;
     const std::vector<uint32_t> caller(primes, primes + n_primes);
     SieveOut &so = ctx->h_out;
@@ -337,7 +337,7 @@ int cuboid_root_check(cuboid_ctx *ctx, const uint32_t *p, const uint32_t *q, uin
     if (n >= (1ull << 32)) return CUBOID_E_LIMIT;
     for (uint64_t i = 0; i < n; ++i)
         if (p[i] >= (1u << 31) || q[i] >= (1u << 31)) return CUBOID_E_LIMIT;
-    std::lock_guard<std::recursive_mutex> g(ctx->mu);
+    CtxLock g(ctx);
     if (set_device(ctx)) return CUBOID_E_DEVICE;
     hipStream_t s = ctx->stream;
     DevBuf dpq, dcand, dpre, dhits, dnh;
@@ -407,14 +407,14 @@ int cuboid_root_check(cuboid_ctx *ctx, const uint32_t *p, const uint32_t *q, uin
 
 int cuboid_enable_timing(cuboid_ctx *ctx, int on) {
     if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
-    std::lock_guard<std::recursive_mutex> g(ctx->mu);
+    CtxLock g(ctx);
     ctx->timing = on != 0;
     return CUBOID_OK;
 }
 
 int cuboid_enable_graphs(cuboid_ctx *ctx, int on) {
     if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
-    std::lock_guard<std::recursive_mutex> g(ctx->mu);
+    CtxLock g(ctx);
     if (set_device(ctx)) return CUBOID_E_DEVICE;
     ctx->use_graphs = on != 0;
     if (!ctx->use_graphs) drop_graphs(ctx);
@@ -424,7 +424,7 @@ int cuboid_enable_graphs(cuboid_ctx *ctx, int on) {
 int cuboid_last_timing(cuboid_ctx *ctx, cuboid_timing *out) {
     if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
     if (!out) return CUBOID_E_ARG;
-    std::lock_guard<std::recursive_mutex> g(ctx->mu);
+    CtxLock g(ctx);
     *out = ctx->last;
     return CUBOID_OK;
 }
@@ -435,7 +435,7 @@ int cuboid_set_tuning(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes
     std::vector<uint32_t> sorted;
     int st = canonical_primes(primes, n_primes, &sorted);
     if (st) return st;
-    std::lock_guard<std::recursive_mutex> g(ctx->mu);
+    CtxLock g(ctx);
     if (!tuning) { ctx->tunings.erase(sorted); return CUBOID_OK; }
     if (tuning->dense_primes > (uint32_t)kKMax && tuning->dense_primes != 0xffffffffu)
         return CUBOID_E_ARG;
@@ -450,7 +450,7 @@ int cuboid_get_tuning(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes
     std::vector<uint32_t> sorted;
     int st = canonical_primes(primes, n_primes, &sorted);
     if (st) return st;
-    std::lock_guard<std::recursive_mutex> g(ctx->mu);
+    CtxLock g(ctx);
     if (set_device(ctx)) return CUBOID_E_DEVICE;
     Plan *pl = nullptr;
     st = build_plan(ctx, sorted, &pl);

@@ -76,7 +76,7 @@ extern "C" int cuboid_autotune(cuboid_ctx *ctx, const uint32_t *primes, uint32_t
     std::vector<uint32_t> sorted;
     int st = canonical_primes(primes, n_primes, &sorted);
     if (st) return st;
-    std::lock_guard<std::recursive_mutex> g(ctx->mu);
+    CtxLock g(ctx);
     if (hipSetDevice(ctx->device) != hipSuccess) return CUBOID_E_DEVICE;
     const std::string arch(ctx->arch), key = prime_key(sorted);
     cuboid_tuning best;

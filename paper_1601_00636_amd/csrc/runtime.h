@@ -111,6 +111,8 @@ struct cuboid_ctx {
     hipStream_t stream = nullptr;
     std::recursive_mutex mu;
     std::atomic<int> servers{0};
+    std::atomic<int> searches{0};
+    std::atomic<int> waiting{0};        // callers blocked on mu (see CtxLock)
     int cu_count = 0;
     size_t max_lds = 0;
     char arch[64] = {0};
@@ -159,6 +161,21 @@ struct cuboid_ctx {
 };
 
 namespace cuboid {
+
+// A caller's hold on a context.  The wait is announced so that background
+// loops that take the context step after step (the search thread) let
+// callers in between their steps instead of re-taking it at once.
+struct CtxLock {
+    cuboid_ctx *c;
+    explicit CtxLock(cuboid_ctx *x) : c(x) {
+        c->waiting.fetch_add(1);
+        c->mu.lock();
+        c->waiting.fetch_sub(1);
+    }
+    ~CtxLock() { c->mu.unlock(); }
+    CtxLock(const CtxLock &) = delete;
+    CtxLock &operator=(const CtxLock &) = delete;
+};
 
 const char *status_text(int s);
 bool ctx_is_live(cuboid_ctx *ctx);

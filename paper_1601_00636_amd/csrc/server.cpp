@@ -157,7 +157,7 @@ void admit(cuboid_server *S) {
             if (!all_idle(S)) return;
             int st;
             {
-                std::lock_guard<std::recursive_mutex> g(ctx->mu);
+                CtxLock g(ctx);
                 st = ensure_rows_serving(ctx, r.rect.p1);
             }
             if (st) {
@@ -472,7 +472,7 @@ int cuboid_server_start(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_prim
     if (c.hbm_budget_bytes == 0) c.hbm_budget_bytes = 1ull << 30;
     S->cfg = c;
     memset(&S->stats, 0, sizeof(S->stats));
-    std::lock_guard<std::recursive_mutex> g(ctx->mu);
+    CtxLock g(ctx);
     if (hipSetDevice(ctx->device) != hipSuccess) return CUBOID_E_DEVICE;
     st = build_plan(ctx, sorted, &S->pl);
     if (st) return st;

@@ -89,6 +89,15 @@ def test_calls_on_null_context_are_refused():
     with pytest.raises(cb.CuboidError) as e:
         cb.cuboid_root_check(bogus, [1], [2])
     assert e.value.status == cb.E_NOT_LOADED
+    with pytest.raises(cb.CuboidError) as e:
+        cb.cuboid_sieve_region(h, 1, 10, [11])
+    assert e.value.status == cb.E_NOT_LOADED
+    with pytest.raises(cb.CuboidError) as e:
+        cb.cuboid_search_start(bogus, [11], 152, 3)
+    assert e.value.status == cb.E_NOT_LOADED
+    with pytest.raises(cb.CuboidError) as e:
+        cb.cuboid_enable_graphs(h, True)
+    assert e.value.status == cb.E_NOT_LOADED
 
 
 def test_bench_refuses_more_than_one_gpu():
