@@ -51,7 +51,9 @@ typedef enum cuboid_status {
     CUBOID_E_CAPACITY = 5,    /* output buffer too small; required size returned  */
     CUBOID_E_NOT_LOADED = 6,  /* null or destroyed context                        */
     CUBOID_E_DEVICE = 7,      /* no usable gfx950 device, or a HIP runtime error  */
-    CUBOID_E_ARG = 8          /* null pointer or invalid argument                 */
+    CUBOID_E_ARG = 8,         /* null pointer or invalid argument                 */
+    CUBOID_E_IO = 9,          /* a file could not be opened, read or written      */
+    CUBOID_E_DATA = 10        /* file contents differ from the tables they name   */
 } cuboid_status;
 
 typedef struct cuboid_ctx cuboid_ctx;
@@ -321,6 +323,42 @@ int cuboid_set_tuning(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes
                       const cuboid_tuning *tuning);
 int cuboid_get_tuning(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes,
                       cuboid_tuning *out);
+
+/* ------------------------------------------------------------- table files */
+
+/*
+ * The paper's binary table files (section 2, eq. 2.7; section 3
+ * Write_pq_file_stream; section 4 Load_Cuboid_Binaries).
+ *
+ * tables file: the packed tables u_r of the primes, ascending, one after the
+ *   other, each in the layout of eq. (2.6) (ceil(r*r/8) bytes).
+ * primes file: one 8-byte item per prime, as the paper's C++ struct
+ *   {short prime; unsigned int p_offset;} lays out on x86: int16 prime
+ *   (little-endian), 2 zero bytes of padding, uint32 byte offset of its table
+ *   in the tables file (little-endian).
+ * text file (may be NULL): each table as "r = <r>" followed by r lines of r
+ *   space-separated 0/1 digits (row p~, column q~, as printed in eq. 2.5) and
+ *   an empty line.
+ * The primes must be below 32768 (int16) and the tables must fit 2^32 bytes,
+ * the bound (2.7) (in practice r < 9697).
+ * Errors: E_PRIMES, E_LIMIT (a prime >= 32768 or tables beyond 2^32 bytes),
+ * E_IO, E_DEVICE, E_NOT_LOADED, E_ARG.
+ */
+int cuboid_write_table_files(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes,
+                             const char *tables_path, const char *primes_path,
+                             const char *text_path);
+
+/*
+ * Reads a tables file and a primes file in the format above and checks them
+ * bit for bit against the tables computed on the device; on success writes
+ * the primes (in file order) to primes_out and their number to *n_primes.
+ * Errors: E_IO (missing, unreadable or truncated file), E_DATA (offsets not
+ * contiguous from 0, padding not zero, or a table that differs), E_PRIMES (an
+ * entry that is not a prime, or a repeated prime), E_CAPACITY (cap smaller
+ * than the number of primes; *n_primes set), E_DEVICE, E_NOT_LOADED, E_ARG.
+ */
+int cuboid_check_table_files(cuboid_ctx *ctx, const char *tables_path, const char *primes_path,
+                             uint32_t *primes_out, uint32_t cap, uint32_t *n_primes);
 
 /* ------------------------------------------------------------------ search */
 

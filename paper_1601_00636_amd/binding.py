@@ -13,7 +13,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcuboid.so")
 
-OK, E_BUSY, E_RANGE, E_LIMIT, E_PRIMES, E_CAPACITY, E_NOT_LOADED, E_DEVICE, E_ARG = range(9)
+(OK, E_BUSY, E_RANGE, E_LIMIT, E_PRIMES, E_CAPACITY, E_NOT_LOADED, E_DEVICE, E_ARG, E_IO,
+ E_DATA) = range(11)
 
 u8, u32, u64, i32 = ctypes.c_uint8, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
 P = ctypes.POINTER
@@ -106,6 +107,10 @@ def _load():
         "cuboid_enable_timing": ([vp, i32], i32),
         "cuboid_last_timing": ([vp, P(cuboid_timing)], i32),
         "cuboid_enable_graphs": ([vp, i32], i32),
+        "cuboid_write_table_files": ([vp, P(u32), u32, ctypes.c_char_p, ctypes.c_char_p,
+                                      ctypes.c_char_p], i32),
+        "cuboid_check_table_files": ([vp, ctypes.c_char_p, ctypes.c_char_p, P(u32), u32, P(u32)],
+                                     i32),
         "cuboid_search_start": ([vp, P(u32), u32, u32, u32, u32, ctypes.c_char_p, P(vp)], i32),
         "cuboid_search_current": ([vp, P(cuboid_search_report)], i32),
         "cuboid_search_survivors": ([vp, P(u64), u64, P(u64)], i32),
@@ -229,6 +234,24 @@ def cuboid_sieve_region(ctx, p0, p1, primes, band_rows=100, cap=1 << 16, stream=
     return dict(counts=counts[:len(pr)], n_pairs=npairs.value, n_survivors=ns.value,
                 survivors=[(int(x >> np.uint64(32)), int(x & np.uint64(0xffffffff))) for x in sv],
                 r_max=rmax[:n_bands].copy())
+
+
+def cuboid_write_table_files(ctx, primes, tables_path, primes_path, text_path=None):
+    pr = _arr(primes, np.uint32)
+    enc = lambda x: x.encode() if x else None
+    _check(_load().cuboid_write_table_files(ctx, _p(pr, u32), len(pr), enc(tables_path),
+                                            enc(primes_path), enc(text_path)),
+           "cuboid_write_table_files")
+
+
+def cuboid_check_table_files(ctx, tables_path, primes_path, cap=6542):
+    """Checks the files against the device's tables; returns their prime list."""
+    out = np.zeros(max(1, cap), dtype=np.uint32)
+    n = u32(0)
+    st = _load().cuboid_check_table_files(ctx, tables_path.encode(), primes_path.encode(),
+                                          _p(out, u32), int(cap), ctypes.byref(n))
+    _check(st, "cuboid_check_table_files", needed=n.value if st == E_CAPACITY else None)
+    return [int(x) for x in out[:n.value]]
 
 
 def cuboid_search_start(ctx, primes, p=152, q=3, p_end=0, report_path=None):

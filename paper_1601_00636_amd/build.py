@@ -22,6 +22,7 @@ SOURCES = [
     "graph.cpp",
     "region.cpp",
     "search.cpp",
+    "tables_io.cpp",
     "context.cpp",
     "autotune.cpp",
     "server.cpp",

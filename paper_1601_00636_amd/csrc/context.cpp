@@ -27,6 +27,8 @@ const char *status_text(int s) {
         case CUBOID_E_NOT_LOADED: return "context not loaded";
         case CUBOID_E_DEVICE: return "device or HIP runtime error";
         case CUBOID_E_ARG: return "invalid argument";
+        case CUBOID_E_IO: return "file input/output error";
+        case CUBOID_E_DATA: return "file contents differ from the tables";
         default: return "unknown status";
     }
 }

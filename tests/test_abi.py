@@ -26,8 +26,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings_and_version():
     assert cb.cuboid_version().endswith("gfx950")
-    for s in range(9):
-        assert cb.cuboid_status_string(s)
+    for s in range(11):
+        assert cb.cuboid_status_string(s) and "unknown" not in cb.cuboid_status_string(s)
     assert "unknown" in cb.cuboid_status_string(99)
 
 
@@ -97,6 +97,9 @@ def test_calls_on_null_context_are_refused():
     assert e.value.status == cb.E_NOT_LOADED
     with pytest.raises(cb.CuboidError) as e:
         cb.cuboid_enable_graphs(h, True)
+    assert e.value.status == cb.E_NOT_LOADED
+    with pytest.raises(cb.CuboidError) as e:
+        cb.cuboid_write_table_files(h, [11], "/nonexistent/t.bin", "/nonexistent/p.bin")
     assert e.value.status == cb.E_NOT_LOADED
 
 
