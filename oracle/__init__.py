@@ -53,6 +53,8 @@ def _load():
     lib.oracle_coeffs_mod_r.restype = None
     lib.oracle_table.argtypes = [u32, P(ctypes.c_uint8)]
     lib.oracle_table.restype = i32
+    lib.oracle_u_entry.argtypes = [u32, u32, u32]
+    lib.oracle_u_entry.restype = i32
     lib.oracle_pack.argtypes = [u32, P(ctypes.c_uint8), P(ctypes.c_uint8)]
     lib.oracle_pack.restype = u64
     lib.oracle_sieve.argtypes = [u32, u32, u32, u32, P(u32), u32, P(P(ctypes.c_uint8)),
@@ -117,18 +119,22 @@ def _tables_arg(primes):
     return arr, tabs
 
 
-def sieve(p0, p1, q0, q1, primes, cap=1 << 20, threads=0):
+def sieve(p0, p1, q0, q1, primes, cap=1 << 20, threads=0, direct=False):
     """The sieve over p0..p1 x q0..q1 (inclusive) with the given primes.
 
     Returns dict(counts (in the order `primes` was given), survivors (sorted
     uint64 pair indices, at most `cap`), n_survivors, n_pairs).  Primes are
     tested in ascending order, so each count is the number of pairs whose first
-    rejecting prime is that one.
+    rejecting prime is that one.  direct=True builds no tables: each bit the
+    walk needs is evaluated from Definition 1.1 (for large primes).
     """
     primes = [int(r) for r in primes]
     order = sorted(range(len(primes)), key=lambda i: primes[i])
     asc = np.array([primes[i] for i in order], dtype=np.uint32)
-    tabs_arr, _keep = _tables_arg(asc)
+    if direct:
+        tabs_arr, _keep = None, None
+    else:
+        tabs_arr, _keep = _tables_arg(asc)
     counts = np.zeros(max(1, len(asc)), dtype=np.uint64)
     surv = np.zeros(max(1, cap), dtype=np.uint64)
     n_pairs = ctypes.c_uint64(0)
@@ -145,6 +151,11 @@ def sieve(p0, p1, q0, q1, primes, cap=1 << 20, threads=0):
     ns = n_surv.value
     return dict(counts=out_counts, survivors=surv[:min(ns, cap)].copy(),
                 n_survivors=ns, n_pairs=n_pairs.value)
+
+
+def u_entry(a, b, r):
+    """u_r(a, b) from Definition 1.1 (r evaluations of Q mod r)."""
+    return int(_load().oracle_u_entry(int(a), int(b), int(r)))
 
 
 def region_qmin(p):

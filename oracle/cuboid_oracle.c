@@ -13,6 +13,9 @@
  * What each function follows:
  *   oracle_coeffs_mod_r / oracle_q_mod_r  eq. (1.1) reduced modulo r, eq. (2.2)
  *   oracle_table                          Definition 1.1 and eq. (2.3)
+ *   oracle_u_entry                        one entry of Definition 1.1, for
+ *                                         primes whose whole table is too
+ *                                         large to build
  *   oracle_pack                           the byte packing of eq. (2.6)
  *   oracle_sieve                          section 2 (the bit sieve) restricted to
  *                                         the domain of Conjecture 1.1
@@ -156,6 +159,17 @@ uint64_t oracle_pack(uint32_t r, const uint8_t *u, uint8_t *out)
     return nbytes;
 }
 
+/*
+ * u_r(a, b) for one entry, from Definition 1.1: 1 iff no t in [0, r) has
+ * Q_ab(t) = 0 mod r.  r evaluations of oracle_q_mod_r.
+ */
+int oracle_u_entry(uint32_t a, uint32_t b, uint32_t r)
+{
+    for (uint64_t t = 0; t < r; ++t)
+        if (oracle_q_mod_r(a, b, t, r) == 0) return 0;
+    return 1;
+}
+
 /* greatest common divisor, Euclid */
 static uint64_t gcd_u64(uint64_t a, uint64_t b)
 {
@@ -176,7 +190,9 @@ static int cmp_u64(const void *x, const void *y)
  * *n_pairs.  Each such pair is tested against the tables of `primes` (which the
  * caller passes in ascending order, with their unpacked tables `tables[i]`,
  * r_i*r_i bytes each) in that order; the first prime whose unsolvability bit
- * u_r(p mod r, q mod r) is 1 rejects the pair and counts[i] is incremented.  A
+ * u_r(p mod r, q mod r) is 1 rejects the pair and counts[i] is incremented.
+ * With tables == NULL every bit the walk needs is evaluated by oracle_u_entry
+ * instead (prime lists whose tables are too large to build).  A
  * pair no prime rejects is a survivor, reported as the index
  * (p - p0) * (q1 - q0 + 1) + (q - q0); survivors come back ascending.
  *
@@ -223,7 +239,9 @@ int oracle_sieve(uint32_t p0, uint32_t p1, uint32_t q0, uint32_t q1,
                 int rejected = 0;
                 for (uint32_t i = 0; i < n_primes; ++i) {
                     uint64_t r = primes[i];
-                    if (tables[i][(p % r) * r + (q % r)]) { cnt[i] += 1; rejected = 1; break; }
+                    const int u = tables ? tables[i][(p % r) * r + (q % r)]
+                                         : oracle_u_entry((uint32_t)(p % r), (uint32_t)(q % r), (uint32_t)r);
+                    if (u) { cnt[i] += 1; rejected = 1; break; }
                 }
                 if (!rejected) {
                     if (tn[tid] == tcap[tid]) {

@@ -396,3 +396,41 @@ def test_theorem_1_1_flags():
     # (1 + 5)(2 + 5) = 42 > 50 is false
     assert poly.theorem_1_1_flags(1, 2, 5) & 8 == 0
     assert poly.theorem_1_1_flags(2, 1, 3) == 2 | 4 | 8
+
+
+# ---------------------------------------------------------------- table-free oracle
+
+@pytest.mark.parametrize("r", [11, 13, 29, 97])
+def test_u_entry_equals_the_tables(r):
+    # the u_11 table is pinned to the paper's print; the entry function must
+    # agree with the tables everywhere
+    u = oracle.table(r)
+    for a in range(r):
+        for b in range(r):
+            assert oracle.u_entry(a, b, r) == u[a, b], (r, a, b)
+
+
+@pytest.mark.parametrize("r", [9697, 65521])
+def test_u_entry_invariants_for_large_primes(r):
+    # u(a, b) = u(b, a) (inversion identity), u(la, lb) = u(a, b) (weight 20),
+    # zero row, column and diagonal (Q(0) = -(pq)^10; Q_pp has the root p^2)
+    rng = np.random.Generator(np.random.PCG64(r))
+    for _ in range(6):
+        a, b, lam = (int(x) for x in rng.integers(1, r, size=3))
+        u = oracle.u_entry(a, b, r)
+        assert oracle.u_entry(b, a, r) == u
+        assert oracle.u_entry(lam * a % r, lam * b % r, r) == u
+        assert oracle.u_entry(0, b, r) == oracle.u_entry(a, 0, r) == oracle.u_entry(a, a, r) == 0
+
+
+def test_direct_sieve_equals_table_sieve():
+    for rect, primes in (((1, 200, 1, 200), [3, 5, 7, 11, 13, 17, 19, 23, 29, 31]),
+                         ((50, 170, 300, 420), [47, 11, 13, 101, 17, 199, 19, 23, 97])):
+        a = oracle.sieve(*rect, primes)
+        b = oracle.sieve(*rect, primes, direct=True)
+        assert a["n_pairs"] == b["n_pairs"]
+        assert list(a["counts"]) == list(b["counts"])
+        assert list(a["survivors"]) == list(b["survivors"])
+    g = json.load(open(golden_path("oracle_c1.json")))
+    d = oracle.sieve(1, 200, 1, 200, g["primes"], direct=True)
+    assert [int(c) for c in d["counts"]] == g["counts"] and d["n_survivors"] == g["n_survivors"]
