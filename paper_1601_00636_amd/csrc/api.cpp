@@ -201,7 +201,7 @@ int cuboid_sieve_range(cuboid_ctx *ctx, uint32_t p0, uint32_t p1, uint32_t q0, u
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
     st = sieve_rects(ctx, caller, &rect, 1, cap, s, &so);
     if (st) return st;
-    memcpy(counts, so.counts.data(), n_primes * 8);
+    memcpy(counts, so.counts, n_primes * 8);
     *n_pairs = so.pairs[0];
     *n_survivors = so.n_surv;
     if (so.n_surv > cap) return CUBOID_E_CAPACITY;
@@ -262,7 +262,7 @@ int cuboid_sieve_batch(cuboid_ctx *ctx, const cuboid_request *req, uint32_t n_re
         if (st && st != CUBOID_E_LIMIT) return st;
     }
     for (uint32_t i = 0; i < n_req; ++i) {
-        memcpy(res[i].counts, so.counts.data() + (size_t)i * n_primes, n_primes * 8);
+        memcpy(res[i].counts, so.counts + (size_t)i * n_primes, n_primes * 8);
         res[i].n_pairs = so.pairs[i];
     }
     if (st == CUBOID_E_LIMIT || so.surv.size() != so.n_surv) {

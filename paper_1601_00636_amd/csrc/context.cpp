@@ -458,9 +458,13 @@ int rect_valid(uint32_t p0, uint32_t p1, uint32_t q0, uint32_t q1) {
 // else from row windows of kBandRows rows computed on the fly, each
 // descriptor split at window edges.
 int sieve_core(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid_tuning &tun,
-               std::vector<ReqDesc> &reqs, uint32_t n_slots, uint64_t surv_cap, hipStream_t s,
-               CoreOut *out) {
+               std::vector<ReqDesc> &reqs, uint32_t n_slots, const std::vector<int32_t> *col,
+               uint64_t surv_cap, hipStream_t s, CoreOut *out) {
     const uint32_t nc = ds.K + ds.n_deep;
+    // counters come back per slot either canonical (nc) or already in the
+    // caller's prime order (col: the counter of each caller prime, -1 for a
+    // trivial one), gathered on the device
+    const uint32_t width = col ? (uint32_t)col->size() : nc;
     int st = ensure_scratch(ctx, n_slots, nc, surv_cap);
     if (st) return st;
     uint32_t pmax = 0;
@@ -472,7 +476,7 @@ int sieve_core(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid
     }
     out->units = 0;
     out->sweep_ms = 0;
-    const size_t ncount = (size_t)n_slots * nc;
+    const size_t ncount = (size_t)n_slots * width;
     ctx->last_graph = 0;
     auto sweep_time = [&]() -> int {
         if (!ctx->timing) return CUBOID_OK;
@@ -491,7 +495,7 @@ int sieve_core(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid
     }
     if (resident && ctx->use_graphs) {
         // clears, sweep, replica sums and downloads all inside the graph
-        st = run_batch_graph(ctx, pl, ds, tun, reqs, n_slots, surv_cap, s, &out->units);
+        st = run_batch_graph(ctx, pl, ds, tun, reqs, n_slots, col, surv_cap, s, &out->units);
         if (st) return st;
         HIPCHK(hipStreamSynchronize(s));
         st = sweep_time();
@@ -543,11 +547,21 @@ int sieve_core(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid
         }
         st = reduce_scratch(ctx, n_slots, nc, s);
         if (st) return st;
+        const void *csrc = ctx->counts.p;
+        if (col && ncount) {
+            HIPCHK(ctx->colbuf.ensure(width * 4));
+            HIPCHK(ctx->gathered.ensure(ncount * 8));
+            HIPCHK(hipMemcpyAsync(ctx->colbuf.p, col->data(), width * 4, hipMemcpyHostToDevice, s));
+            HIPCHK(launch_gather_counts((const unsigned long long *)ctx->counts.p,
+                                        (const int32_t *)ctx->colbuf.p, n_slots, nc, width,
+                                        (unsigned long long *)ctx->gathered.p, s));
+            csrc = ctx->gathered.p;
+        }
         // results through pinned staging: counts, pairs, survivor count
         HIPCHK(ctx->result_stage.ensure((ncount + n_slots + 1) * 8));
         uint64_t *rs = (uint64_t *)ctx->result_stage.p;
         if (ncount)
-            HIPCHK(hipMemcpyAsync(rs, ctx->counts.p, ncount * 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(rs, csrc, ncount * 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(rs + ncount, ctx->pairs.p, (size_t)n_slots * 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(rs + ncount + n_slots, ctx->surv_n.p, 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -555,8 +569,9 @@ int sieve_core(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid
     const uint64_t *stage = (const uint64_t *)ctx->result_stage.p;
     out->nc = nc;
     out->n_slots = n_slots;
-    out->counts.assign(stage, stage + ncount);
-    out->pairs.assign(stage + ncount, stage + ncount + n_slots);
+    out->width = width;
+    out->counts = stage;
+    out->pairs = stage + ncount;
     out->n_surv = stage[ncount + n_slots];
     out->surv.clear();
     if (out->n_surv > 0 && out->n_surv <= surv_cap) {
@@ -613,22 +628,15 @@ int sieve_rects(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes,
         d.slot = i;
     }
     if (ctx->timing) HIPCHK(hipEventRecord(ctx->ev_total0, s));
-    CoreOut &co = ctx->h_core;
-    st = sieve_core(ctx, *pl, *ds, tun, reqs, n_req, surv_cap, s, &co);
-    if (st) return st;
-    const uint32_t nc = co.nc;
-    const uint32_t np = (uint32_t)caller_primes.size();
     const std::vector<int32_t> col = count_columns(*pl, caller_primes);
+    CoreOut &co = ctx->h_core;
+    st = sieve_core(ctx, *pl, *ds, tun, reqs, n_req, &col, surv_cap, s, &co);
+    if (st) return st;
     out->n_req = n_req;
-    out->n_primes = np;
+    out->n_primes = (uint32_t)caller_primes.size();
     out->n_surv = co.n_surv;
-    out->counts.assign((size_t)n_req * np, 0);
-    for (uint32_t i = 0; i < n_req; ++i) {
-        const uint64_t *c = co.counts.data() + (size_t)i * nc;
-        uint64_t *o = out->counts.data() + (size_t)i * np;
-        for (uint32_t j = 0; j < np; ++j) o[j] = col[j] < 0 ? 0 : c[col[j]];
-    }
-    out->pairs.assign(co.pairs.begin(), co.pairs.end());
+    out->counts = co.counts;
+    out->pairs = co.pairs;
     out->surv.assign(co.surv.begin(), co.surv.end());
     record_timing(ctx, s, co, *ds, tun);
     if (co.n_surv > surv_cap && surv_cap < surv_cap_total) return CUBOID_E_LIMIT;

@@ -29,17 +29,19 @@ constexpr size_t kMaxGraphs = 8;         // cached graphs per context
 constexpr uint64_t kMinOrderRows = 1u << 20;
 
 struct Layout {
-    size_t o_desc, o_cpre, o_rpre, bytes;
+    size_t o_desc, o_cpre, o_rpre, o_col, bytes;
 };
 
 // Request block, identical in pinned staging and on the device:
-// header | descriptors [n] | chunk prefix [n + 1] | row prefix [n + 1]
-Layout layout_of(uint32_t n) {
+// header | descriptors [n] | chunk prefix [n + 1] | row prefix [n + 1] |
+// counter column of each caller prime [np] (int32, padded to 8 bytes)
+Layout layout_of(uint32_t n, uint32_t np) {
     Layout L;
     L.o_desc = kHdrBytes;
     L.o_cpre = L.o_desc + (size_t)n * sizeof(ReqDesc);
     L.o_rpre = L.o_cpre + (size_t)(n + 1) * 8;
-    L.bytes = L.o_rpre + (size_t)(n + 1) * 8;
+    L.o_col = L.o_rpre + (size_t)(n + 1) * 8;
+    L.bytes = L.o_col + ((size_t)np * 4 + 7) / 8 * 8;
     return L;
 }
 
@@ -71,7 +73,8 @@ struct GraphArgs {
     uint64_t *result;
     uint32_t *order;
     Layout L;
-    uint32_t n, n_slots, nc, grid;
+    uint32_t n, n_slots, nc, np, grid;
+    bool gather;                  // counts come back in the caller's prime order
     size_t lds;
     uint32_t max_p;
     bool timing;
@@ -80,6 +83,7 @@ struct GraphArgs {
 hipError_t build_graph(cuboid_ctx *ctx, const GraphArgs &a, hipStream_t s, BatchGraph *out) {
     const uint32_t n = a.n, ns = a.n_slots, nc = a.nc;
     const uint64_t ncount = (uint64_t)ns * nc;
+    const uint64_t nout = (uint64_t)ns * (a.gather ? a.np : nc);
     hipGraph_t pre = nullptr, sweep = nullptr, post = nullptr, parent = nullptr;
     hipGraphExec_t exec = nullptr;
     hipError_t e = capture_part(s, &pre, [&]() -> hipError_t {
@@ -103,14 +107,21 @@ hipError_t build_graph(cuboid_ctx *ctx, const GraphArgs &a, hipStream_t s, Batch
             if (r == hipSuccess)
                 r = launch_reduce_replicas((unsigned long long *)ctx->pairs.p, ns, ctx->n_rep,
                                            ctx->rep_stride_pairs, s);
+            const void *csrc = ctx->counts.p;
+            if (r == hipSuccess && a.gather && nout) {
+                r = launch_gather_counts((const unsigned long long *)ctx->counts.p,
+                                         (const int32_t *)(a.block + a.L.o_col), ns, nc, a.np,
+                                         (unsigned long long *)ctx->gathered.p, s);
+                csrc = ctx->gathered.p;
+            }
             // no counters when every prime is trivial; capture refuses empty copies
-            if (r == hipSuccess && ncount)
-                r = hipMemcpyAsync(a.result, ctx->counts.p, ncount * 8, hipMemcpyDeviceToHost, s);
+            if (r == hipSuccess && nout)
+                r = hipMemcpyAsync(a.result, csrc, nout * 8, hipMemcpyDeviceToHost, s);
             if (r == hipSuccess)
-                r = hipMemcpyAsync(a.result + ncount, ctx->pairs.p, (size_t)ns * 8,
+                r = hipMemcpyAsync(a.result + nout, ctx->pairs.p, (size_t)ns * 8,
                                    hipMemcpyDeviceToHost, s);
             if (r == hipSuccess)
-                r = hipMemcpyAsync(a.result + ncount + ns, ctx->surv_n.p, 8, hipMemcpyDeviceToHost, s);
+                r = hipMemcpyAsync(a.result + nout + ns, ctx->surv_n.p, 8, hipMemcpyDeviceToHost, s);
             return r;
         });
     if (e == hipSuccess) e = hipGraphCreate(&parent, 0);
@@ -162,10 +173,12 @@ void drop_graphs(cuboid_ctx *ctx) {
 
 // Resident-row batch as one graph launch on `s`; the caller synchronizes `s`
 // before reading counts, pair counts and the survivor count from the result
-// staging ([n_slots * nc] counts | [n_slots] pairs | survivor count).
+// staging ([n_slots * width] counts | [n_slots] pairs | survivor count), width
+// being nc, or the caller's prime count when `col` maps them.
 int run_batch_graph(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid_tuning &tun,
-                    std::vector<ReqDesc> &reqs, uint32_t n_slots, uint64_t surv_cap,
-                    hipStream_t s, uint64_t *units_out) {
+                    std::vector<ReqDesc> &reqs, uint32_t n_slots,
+                    const std::vector<int32_t> *col, uint64_t surv_cap, hipStream_t s,
+                    uint64_t *units_out) {
     const uint32_t n = (uint32_t)reqs.size();
     const uint32_t nc = ds.K + ds.n_deep;
     LaunchShape &sh = ctx->h_shape;
@@ -181,13 +194,15 @@ int run_batch_graph(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const c
                             ? (const uint32_t *)ctx->order.p + sh.row_prefix[i] : nullptr;
     const size_t lds = (size_t)ds.words * 8 + kSweepFixedLds;
     if (lds > ctx->max_lds) return CUBOID_E_LIMIT;
-    const Layout L = layout_of(n);
-    const uint64_t ncount = (uint64_t)n_slots * nc;
+    const uint32_t np = col ? (uint32_t)col->size() : 0;
+    const Layout L = layout_of(n, np);
+    const uint64_t nout = (uint64_t)n_slots * (col ? np : nc);
     // the previous reader of the staging buffers on this stream is done once
     // the stream is idle
     if (hipStreamSynchronize(s) != hipSuccess) return CUBOID_E_DEVICE;
     if (ctx->gstage.ensure(L.bytes) != hipSuccess || ctx->gblock.ensure(L.bytes) != hipSuccess ||
-        ctx->result_stage.ensure((ncount + n_slots + 1) * 8) != hipSuccess)
+        ctx->result_stage.ensure((nout + n_slots + 1) * 8) != hipSuccess ||
+        (col && ctx->gathered.ensure(nout * 8 + 8) != hipSuccess))
         return CUBOID_E_DEVICE;
     unsigned char *st = (unsigned char *)ctx->gstage.p;
     const uint64_t hdr[4] = {sh.units, sh.n_chunks, 0, 0};
@@ -195,6 +210,7 @@ int run_batch_graph(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const c
     memcpy(st + L.o_desc, reqs.data(), (size_t)n * sizeof(ReqDesc));
     memcpy(st + L.o_cpre, sh.chunk_prefix.data(), (size_t)(n + 1) * 8);
     memcpy(st + L.o_rpre, sh.row_prefix.data(), (size_t)(n + 1) * 8);
+    if (np) memcpy(st + L.o_col, col->data(), (size_t)np * 4);
 
     GraphArgs a;
     a.block = (unsigned char *)ctx->gblock.p;
@@ -205,6 +221,8 @@ int run_batch_graph(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const c
     a.n = n;
     a.n_slots = n_slots;
     a.nc = nc;
+    a.np = np;
+    a.gather = col != nullptr;
     a.grid = tun.workgroups;
     a.lds = lds;
     a.max_p = sh.max_p;
@@ -222,6 +240,9 @@ int run_batch_graph(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const c
     put(&key, (uint64_t)a.lds);
     put(&key, ctx->n_rep);
     put(&key, n_slots);
+    put(&key, np);
+    put(&key, (uint32_t)a.gather);
+    put(&key, (const void *)ctx->gathered.p);
     put(&key, a.grid);
     put(&key, (uint32_t)sweep_factor_slots(sh.max_p));
     put(&key, (uint32_t)a.timing);

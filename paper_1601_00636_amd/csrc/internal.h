@@ -149,6 +149,9 @@ hipError_t launch_reduce_slots(const unsigned long long *counts, const unsigned 
                                uint64_t stride_c, uint64_t stride_p, unsigned long long *out,
                                hipStream_t s);
 // dst[i] = sum of n_rep replicas src[r * stride + i], in place on replica 0
+hipError_t launch_gather_counts(const unsigned long long *counts, const int32_t *col,
+                                uint32_t n_slots, uint32_t nc, uint32_t np,
+                                unsigned long long *out, hipStream_t s);
 hipError_t launch_reduce_replicas(unsigned long long *buf, uint64_t n, uint32_t n_rep,
                                   uint64_t stride, hipStream_t s);
 // max_p: the largest row coordinate of the launch (selects the factor slots)

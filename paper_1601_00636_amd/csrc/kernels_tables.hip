@@ -295,6 +295,20 @@ __global__ void reduce_slots_kernel(const unsigned long long *counts,
     }
 }
 
+// Per-slot counters (canonical order, nc per slot) into the caller's prime
+// order (np per slot): out[i][j] = counts[i][col[j]], 0 where col[j] < 0.
+__global__ void gather_counts_kernel(const unsigned long long *counts, const int32_t *col,
+                                     uint32_t n_slots, uint32_t nc, uint32_t np,
+                                     unsigned long long *out) {
+    const uint64_t n = (uint64_t)n_slots * np;
+    for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < n;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t i = g / np;
+        const int32_t c = col[g - i * np];
+        out[g] = c < 0 ? 0ull : counts[i * nc + (uint32_t)c];
+    }
+}
+
 __global__ void reduce_replicas_kernel(unsigned long long *buf, uint64_t n, uint32_t n_rep,
                                        uint64_t stride) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
@@ -429,6 +443,16 @@ hipError_t launch_reduce_slots(const unsigned long long *counts, const unsigned 
     const uint64_t work = (uint64_t)n * (nc + 1);
     hipLaunchKernelGGL(reduce_slots_kernel, dim3(grid_for(work)), dim3(kBlock), 0, s, counts, pairs,
                        slots, n, nc, n_rep, stride_c, stride_p, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_counts(const unsigned long long *counts, const int32_t *col,
+                                uint32_t n_slots, uint32_t nc, uint32_t np,
+                                unsigned long long *out, hipStream_t s) {
+    const uint64_t n = (uint64_t)n_slots * np;
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(gather_counts_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, counts, col,
+                       n_slots, nc, np, out);
     return hipGetLastError();
 }
 

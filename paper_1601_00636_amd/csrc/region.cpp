@@ -88,12 +88,12 @@ int region_sieve(cuboid_ctx *ctx, uint32_t p0, uint32_t p1, uint32_t band_rows,
             }
         }
         CoreOut &co = ctx->h_core;
-        st = sieve_core(ctx, *pl, *ds, tun, reqs, nb, surv_cap, s, &co);
+        st = sieve_core(ctx, *pl, *ds, tun, reqs, nb, nullptr, surv_cap, s, &co);
         if (st) return st;
         sum.units += co.units;
         sum.sweep_ms += co.sweep_ms;
         for (uint32_t j = 0; j < nb; ++j) {
-            const uint64_t *c = co.counts.data() + (size_t)j * co.nc;
+            const uint64_t *c = co.counts + (size_t)j * co.width;
             uint64_t rejected = 0;
             uint32_t deepest = 0;
             for (uint32_t k = 0; k < co.nc; ++k) {

@@ -88,8 +88,11 @@ struct BatchGraph {
 // Results of one sweep over descriptors grouped into counter slots.
 struct CoreOut {
     uint32_t nc = 0, n_slots = 0;
-    std::vector<uint64_t> counts;   // [n_slots][nc], non-trivial primes ascending
-    std::vector<uint64_t> pairs;    // [n_slots]
+    uint32_t width = 0;             // counters per slot: nc, or the caller's primes
+    // in the pinned result staging, valid until the next call on the context:
+    const uint64_t *counts = nullptr;   // [n_slots][width]: non-trivial primes
+                                        // ascending, or the caller's order
+    const uint64_t *pairs = nullptr;    // [n_slots]
     std::vector<SurvEntry> surv;    // sorted by (slot, idx), when all fit the scratch
     uint64_t n_surv = 0;
     uint64_t units = 0;
@@ -98,8 +101,8 @@ struct CoreOut {
 // Results of one sieve call over several rectangles.
 struct SieveOut {
     uint32_t n_req = 0, n_primes = 0;
-    std::vector<uint64_t> counts;   // [n_req][n_primes], caller's prime order
-    std::vector<uint64_t> pairs;    // [n_req]
+    const uint64_t *counts = nullptr;   // [n_req][n_primes], caller's prime order
+    const uint64_t *pairs = nullptr;    // [n_req] (both in the result staging)
     std::vector<SurvEntry> surv;    // all survivors sorted by (request, index), if fetched
     uint64_t n_surv = 0;            // survivors of the whole call
 };
@@ -134,6 +137,7 @@ struct cuboid_ctx {
     // per-call scratch
     cuboid::DevBuf reqbuf, counts, pairs, surv, surv_tmp, surv_n;
     cuboid::DevBuf order, chunk_prefix, row_prefix;   // row regrouping
+    cuboid::DevBuf colbuf, gathered;    // counter columns of the caller's primes
     uint32_t n_rep = 1;                 // counter replicas of the current call
     uint64_t rep_stride_counts = 0, rep_stride_pairs = 0;
     bool bucketing = true;
@@ -191,8 +195,8 @@ cuboid_tuning tuning_for(cuboid_ctx *ctx, const std::vector<uint32_t> &primes, c
 int rect_valid(uint32_t p0, uint32_t p1, uint32_t q0, uint32_t q1);
 void shape_reqs(cuboid_ctx *ctx, std::vector<ReqDesc> &reqs, LaunchShape *sh);
 int sieve_core(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid_tuning &tun,
-               std::vector<ReqDesc> &reqs, uint32_t n_slots, uint64_t surv_cap, hipStream_t s,
-               CoreOut *out);
+               std::vector<ReqDesc> &reqs, uint32_t n_slots, const std::vector<int32_t> *col,
+               uint64_t surv_cap, hipStream_t s, CoreOut *out);
 int prepare_primes(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes, Plan **pl,
                    cuboid_tuning *tun, DenseSet **ds);
 void record_timing(cuboid_ctx *ctx, hipStream_t s, const CoreOut &co, const DenseSet &ds,
@@ -204,8 +208,9 @@ int region_sieve(cuboid_ctx *ctx, uint32_t p0, uint32_t p1, uint32_t band_rows,
 SweepParams sweep_params(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const ReqDesc *req,
                          uint32_t n_req, uint64_t units, uint64_t surv_cap);
 int run_batch_graph(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid_tuning &tun,
-                    std::vector<ReqDesc> &reqs, uint32_t n_slots, uint64_t surv_cap,
-                    hipStream_t s, uint64_t *units_out);
+                    std::vector<ReqDesc> &reqs, uint32_t n_slots,
+                    const std::vector<int32_t> *col, uint64_t surv_cap, hipStream_t s,
+                    uint64_t *units_out);
 void drop_graphs(cuboid_ctx *ctx);
 int sieve_rects(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes,
                 const cuboid_request *rects, uint32_t n_req, uint64_t surv_cap_total,

@@ -100,7 +100,7 @@ int step(cuboid_search *s, uint32_t p, uint32_t q, uint32_t *p_next) {
         SieveOut &so = ctx->h_out;
         int st = sieve_rects(ctx, s->primes, &rect, 1, kChunkSurvCap, ctx->stream, &so);
         if (st && st != CUBOID_E_LIMIT) return st;
-        memcpy(counts.data(), so.counts.data(), (size_t)n * 8);
+        memcpy(counts.data(), so.counts, (size_t)n * 8);
         pairs = so.pairs[0];
         nsurv = so.n_surv;
         for (const SurvEntry &e : so.surv) surv.push_back(((uint64_t)p << 32) | (q + e.idx));
