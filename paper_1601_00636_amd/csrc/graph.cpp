@@ -24,7 +24,7 @@ namespace cuboid {
 namespace {
 
 constexpr size_t kHdrBytes = 32;         // unit count, chunk count, two unused words
-constexpr uint32_t kBucketGrid = 1024;   // blocks of the regrouping node (grid-stride)
+constexpr uint32_t kBucketGrid = 4096;   // blocks of the regrouping node (grid-stride)
 constexpr size_t kMaxGraphs = 8;         // cached graphs per context
 constexpr uint64_t kMinOrderRows = 1u << 20;
 

@@ -232,36 +232,65 @@ __global__ void row_info_kernel(const uint32_t *primes16, const uint32_t *magic1
 // One block per chunk of kBucketChunk rows of a request: the chunk's rows are
 // written to `order` grouped by their number of factors >= 7, so that the 64
 // rows of a wavefront tend to share that number.
+// Rows of each 8192-row chunk of a request regrouped by their number of prime
+// factors >= 7, stably (ascending p inside each group).  Each of the 4 waves
+// of a block takes a quarter of the chunk: it counts its rows per group with
+// ballots, the block turns the (group, wave) counts into start positions, and
+// each wave places its rows 64 at a time at its running positions.
 __global__ void __launch_bounds__(256) bucket_rows_kernel(const ReqDesc *req, uint32_t n_req,
                                                           const uint64_t *chunk_prefix,
                                                           const uint64_t *row_prefix,
                                                           uint32_t *order, uint64_t n_chunks,
                                                           const uint64_t *n_chunks_dev) {
-    __shared__ uint32_t cnt[kMaxBigFactors + 1];
+    constexpr int kGroups = kMaxBigFactors + 1;
+    constexpr uint32_t kPerWave = kBucketChunk / 4;
+    __shared__ uint32_t cnt[kGroups][4];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint64_t nch = n_chunks_dev ? *n_chunks_dev : n_chunks;
     for (uint64_t b = blockIdx.x; b < nch; b += gridDim.x) {
         const uint32_t i = find_segment(chunk_prefix, n_req, b);
         const ReqDesc R = req[i];
         const uint64_t rows = (uint64_t)R.p1 - R.p0 + 1;
         const uint64_t r0 = (b - chunk_prefix[i]) * kBucketChunk;
-        const uint64_t r1 = r0 + kBucketChunk < rows ? r0 + kBucketChunk : rows;
-        if (threadIdx.x <= (unsigned)kMaxBigFactors) cnt[threadIdx.x] = 0;
-        __syncthreads();
-        for (uint64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x)
-            atomicAdd(&cnt[R.nfac[R.p0 + (uint32_t)r - R.rows_p0]], 1u);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t acc = 0;
-            for (int k = 0; k <= kMaxBigFactors; ++k) { const uint32_t c = cnt[k]; cnt[k] = acc; acc += c; }
+        const uint32_t n = (uint32_t)((r0 + kBucketChunk < rows ? r0 + kBucketChunk : rows) - r0);
+        const uint8_t *nf = R.nfac + (R.p0 + (uint32_t)r0 - R.rows_p0);
+        const uint32_t a = w * kPerWave;
+        const uint32_t e = a + kPerWave < n ? a + kPerWave : n;   // this wave's rows [a, e)
+        uint32_t run[kGroups];
+        for (int k = 0; k < kGroups; ++k) run[k] = 0;
+        for (uint32_t g = a; g < e; g += 64) {
+            const uint32_t r = g + lane;
+            const uint32_t k = r < e ? nf[r] : (uint32_t)kGroups;
+            for (int kk = 0; kk < kGroups; ++kk) run[kk] += (uint32_t)__popcll(__ballot(k == (uint32_t)kk));
         }
+        if (lane == 0)
+            for (int kk = 0; kk < kGroups; ++kk) cnt[kk][w] = run[kk];
         __syncthreads();
+        // start of (group kk, wave w): every row of lower groups, then of this
+        // group in lower waves
+        uint32_t acc = 0;
+        for (int kk = 0; kk < kGroups; ++kk) {
+            uint32_t below = 0;
+            for (uint32_t v = 0; v < 4; ++v)
+                if (v < w) below += cnt[kk][v];
+            run[kk] = acc + below;
+            acc += cnt[kk][0] + cnt[kk][1] + cnt[kk][2] + cnt[kk][3];
+        }
+        __syncthreads();   // cnt is rewritten by the next chunk
         uint32_t *dst = order + row_prefix[i] + r0;
-        for (uint64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-            const uint32_t p = R.p0 + (uint32_t)r;
-            const uint32_t pos = atomicAdd(&cnt[R.nfac[p - R.rows_p0]], 1u);
-            dst[pos] = p;
+        for (uint32_t g = a; g < e; g += 64) {
+            const uint32_t r = g + lane;
+            const uint32_t k = r < e ? nf[r] : (uint32_t)kGroups;
+            uint32_t pos = 0;
+            for (int kk = 0; kk < kGroups; ++kk) {
+                const uint64_t m = __ballot(k == (uint32_t)kk);
+                if (k == (uint32_t)kk)
+                    pos = run[kk] + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                run[kk] += (uint32_t)__popcll(m);
+            }
+            if (k < (uint32_t)kGroups) dst[pos] = R.p0 + (uint32_t)(r0 + r);
         }
-        __syncthreads();   // cnt is cleared for the next chunk of this block
     }
 }
 
