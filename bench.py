@@ -90,9 +90,24 @@ def run_cpu_baseline(reqs, primes, stride):
     for rect in sample:
         pairs += oracle.sieve(*rect, primes, cap=1 << 16, threads=threads)["n_pairs"]
     dt = time.time() - t0
+    # one thread, on the first 8 rectangles of the same sample
+    t1 = time.time()
+    pairs1 = 0
+    for rect in sample[:8]:
+        pairs1 += oracle.sieve(*rect, primes, cap=1 << 16, threads=1)["n_pairs"]
+    dt1 = time.time() - t1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return dict(value=pairs / dt, unit="coprime pairs/s", cores=threads, kind="oracle",
                 sample="every %dth of the 4096 batched rectangles (%d rectangles, %d coprime "
-                       "pairs) in %.1f s; tables excluded" % (stride, len(sample), pairs, dt))
+                       "pairs) in %.1f s; tables excluded" % (stride, len(sample), pairs, dt),
+                single_core={"value": pairs1 / dt1, "sample": "the first 8 of those rectangles "
+                             "(%d coprime pairs) in %.1f s" % (pairs1, dt1)},
+                cpu_model=model, host_threads=os.cpu_count())
 
 
 def calibrate_copy():
@@ -138,6 +153,25 @@ def run_served(cb, wl, ctx, primes, seconds):
             "max_admitted": stats["max_admitted"]}
 
 
+def section6_scan(cb, wl, ctx, stream, torch):
+    """The scan of the paper's section 6: region (1.2), p = 1..154000, the 96
+    primes 11..541, the deepest prime used reported per hundred of p."""
+    pp = wl.PRIMES_PAPER
+    cb.cuboid_sieve_region(ctx, 1, 154000, pp, band_rows=100, stream=stream)
+    reps = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        g6 = cb.cuboid_sieve_region(ctx, 1, 154000, pp, band_rows=100, stream=stream)
+        torch.cuda.synchronize()
+        reps.append(time.perf_counter() - t0)
+    t6 = cb.cuboid_last_timing(ctx)
+    dt = float(np.median(reps))
+    return {"p_range": [1, 154000], "primes": "11..541 (96)", "band_rows": 100,
+            "coprime_pairs": g6["n_pairs"], "survivors": g6["n_survivors"],
+            "deepest_prime": int(g6["r_max"].max()), "ms": dt * 1e3, "sweep_ms": t6["sweep_ms"],
+            "value": g6["n_pairs"] / dt, "paper_hours": 4130 / 60.0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +181,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=64)
     ap.add_argument("--served-seconds", type=float, default=10.0)
+    ap.add_argument("--section6-only", action="store_true",
+                    help="only run the region scan of the paper's section 6 (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -166,6 +202,11 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     ctx = cb.cuboid_create(0)
+    if args.section6_only:
+        cb.cuboid_enable_timing(ctx, True)
+        print(json.dumps(section6_scan(cb, wl, ctx, stream, torch)))
+        cb.cuboid_destroy(ctx)
+        return 0
     reqs = wl.batched_requests(4096)
     primes = wl.PRIMES_BATCHED
     tun = cb.cuboid_autotune(ctx, primes)
@@ -291,24 +332,7 @@ def main():
                                       "sweep_pairs_per_s": r3["n_pairs"] / (t3["sweep_ms"] * 1e-3)}
 
     if not args.no_extras:
-        # the scan of the paper's section 6: region (1.2), p = 1..154000,
-        # primes 11..541, progress reported per hundred of p
-        pp = wl.PRIMES_PAPER
-        cb.cuboid_sieve_region(ctx, 1, 154000, pp, band_rows=100, stream=stream)
-        reps = []
-        for _ in range(3):
-            t0 = time.perf_counter()
-            g6 = cb.cuboid_sieve_region(ctx, 1, 154000, pp, band_rows=100, stream=stream)
-            torch.cuda.synchronize()
-            reps.append(time.perf_counter() - t0)
-        t6 = cb.cuboid_last_timing(ctx)
-        dt = float(np.median(reps))
-        res["extras"]["section6_scan"] = {
-            "p_range": [1, 154000], "primes": "11..541 (96)", "band_rows": 100,
-            "coprime_pairs": g6["n_pairs"], "survivors": g6["n_survivors"],
-            "deepest_prime": int(g6["r_max"].max()), "ms": dt * 1e3, "sweep_ms": t6["sweep_ms"],
-            "value": g6["n_pairs"] / dt,
-            "paper_hours": 4130 / 60.0}
+        res["extras"]["section6_scan"] = section6_scan(cb, wl, ctx, stream, torch)
 
     if not args.no_extras and args.served_seconds > 0:
         res["extras"]["served"] = run_served(cb, wl, ctx, primes, args.served_seconds)

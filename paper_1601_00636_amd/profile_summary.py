@@ -3,6 +3,7 @@
 usage:
   python -m paper_1601_00636_amd.profile_summary trace DB "COMMAND"
   python -m paper_1601_00636_amd.profile_summary traffic FETCH_DB WRITE_DB COPY_FETCH_DB COPY_WRITE_DB "COMMANDS"
+  python -m paper_1601_00636_amd.profile_summary counters DB1,DB2 "COMMANDS" UNITS
 
 `trace`: per-kernel dispatch counts and durations of a --kernel-trace run.
 `traffic`: FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the sweep kernel's
@@ -96,9 +97,32 @@ def traffic(fetch_db, write_db, cfetch_db, cwrite_db, command, launches=4):
     return "".join(md), rec
 
 
+def counters(dbs, command, units):
+    """SQ counters of the largest sweep dispatches, per dispatch and per unit."""
+    rows = {}
+    for db in dbs:
+        c = sqlite3.connect(db)
+        for name, v, d in c.execute(
+                "select counter_name, value, duration from counters_collection where "
+                "kernel_name like '%sweep%' order by duration desc"):
+            rows.setdefault(name, []).append((d, v))
+    out = ["# SQ counters of the sweep kernel (batched 4096-rectangle workload)\n\n",
+           "Commands (one counter group per run):\n\n    %s\n\n" % command.replace(";", "\n   "),
+           "Averages over the 2 largest dispatches (the timed batched launches); "
+           "%d 64x64 units per launch.\n\n" % units,
+           "| counter | per dispatch | per unit |\n|---|---|---|\n"]
+    for name in sorted(rows):
+        top = sorted(rows[name], reverse=True)[:2]
+        v = sum(x[1] for x in top) / len(top)
+        out.append("| %s | %.4g | %.2f |\n" % (name, v, v / units))
+    return "".join(out)
+
+
 def main(argv):
     if argv[0] == "trace":
         print(trace(argv[1], argv[2]))
+    elif argv[0] == "counters":
+        print(counters(argv[1].split(","), argv[2], int(argv[3])))
     elif argv[0] == "traffic":
         md, rec = traffic(argv[1], argv[2], argv[3], argv[4], argv[5])
         print(md)
