@@ -257,7 +257,8 @@ typedef struct cuboid_server_config {
     uint32_t streams;             /* launches in flight at once (0 = 2)                  */
     uint32_t max_slots;           /* requests admitted at once (0 = 4096)                */
     uint64_t max_launch_units;    /* units per launch (0 = 2^20)                         */
-    uint64_t hbm_budget_bytes;    /* device memory for per-request row orders (0 = 1 GiB) */
+    uint64_t hbm_budget_bytes;    /* device memory for per-request row orders; 0 = a      */
+                                  /* quarter of the free device memory, 64 MiB .. 4 GiB   */
 } cuboid_server_config;
 
 typedef struct cuboid_server_stats {

@@ -469,11 +469,16 @@ int cuboid_server_start(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_prim
     if (c.streams > 8) return CUBOID_E_ARG;
     if (c.max_slots == 0) c.max_slots = 4096;
     if (c.max_launch_units == 0) c.max_launch_units = 1u << 20;
-    if (c.hbm_budget_bytes == 0) c.hbm_budget_bytes = 1ull << 30;
-    S->cfg = c;
-    memset(&S->stats, 0, sizeof(S->stats));
     CtxLock g(ctx);
     if (hipSetDevice(ctx->device) != hipSuccess) return CUBOID_E_DEVICE;
+    if (c.hbm_budget_bytes == 0) {
+        // a quarter of the device memory free now, between 64 MiB and 4 GiB
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return CUBOID_E_DEVICE;
+        c.hbm_budget_bytes = std::min<uint64_t>(4ull << 30, std::max<uint64_t>(64ull << 20, free_b / 4));
+    }
+    S->cfg = c;
+    memset(&S->stats, 0, sizeof(S->stats));
     st = build_plan(ctx, sorted, &S->pl);
     if (st) return st;
     S->tun = tuning_for(ctx, sorted, *S->pl);
