@@ -1,0 +1,79 @@
+"""Several host threads on one context, and several contexts at once: every
+result equals the one the same call gives alone (calls on a context are
+serialised; results never depend on concurrency)."""
+import threading
+
+import numpy as np
+import pytest
+
+from paper_1601_00636_amd import binding as cb
+from paper_1601_00636_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _jobs():
+    out = []
+    for j in range(12):
+        rects = wl.random_rectangles(20 + 7 * j, seed=500 + j, max_coord=200000, max_side=1500)
+        primes = wl.PRIMES_C2 if j % 3 else wl.PRIMES_BATCHED
+        out.append((rects, primes))
+    return out
+
+
+def _run(ctx, job):
+    rects, primes = job
+    st, res = cb.cuboid_sieve_batch(ctx, rects, primes, caps=64)
+    one = cb.cuboid_sieve_range(ctx, *rects[0], primes)
+    reg = cb.cuboid_sieve_region(ctx, 3000, 3100, wl.PRIMES_PAPER)
+    return (st, res.counts.copy(), np.array(res.n_pairs), np.array(res.n_survivors),
+            one["n_pairs"], list(one["counts"]), reg["n_pairs"], list(reg["r_max"]))
+
+
+def _same(a, b):
+    assert a[0] == b[0]
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
+    assert a[4:] == b[4:]
+
+
+def _threaded(ctxs, jobs):
+    got = [None] * len(jobs)
+    errs = []
+
+    def work(i):
+        try:
+            got[i] = _run(ctxs[i % len(ctxs)], jobs[i])
+        except Exception as e:        # reported after the join
+            errs.append(e)
+
+    ts = [threading.Thread(target=work, args=(i,)) for i in range(len(jobs))]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join(timeout=120)
+    assert not errs, errs
+    return got
+
+
+def test_threads_share_one_context():
+    ctx = cb.cuboid_create(0)
+    try:
+        jobs = _jobs()
+        alone = [_run(ctx, j) for j in jobs]
+        for _ in range(2):
+            for a, b in zip(_threaded([ctx], jobs), alone):
+                _same(a, b)
+    finally:
+        assert cb.cuboid_destroy(ctx) == cb.OK
+
+
+def test_threads_on_several_contexts():
+    ctxs = [cb.cuboid_create(0) for _ in range(3)]
+    try:
+        jobs = _jobs()
+        alone = [_run(ctxs[0], j) for j in jobs]
+        for a, b in zip(_threaded(ctxs, jobs), alone):
+            _same(a, b)
+    finally:
+        for c in ctxs:
+            assert cb.cuboid_destroy(c) == cb.OK
