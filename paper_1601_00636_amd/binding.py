@@ -207,7 +207,7 @@ def cuboid_sieve_range(ctx, p0, p1, q0, q1, primes, cap=1 << 20, stream=None):
     """dict(counts, n_pairs, survivors, n_survivors); raises CuboidError."""
     pr = _arr(primes, np.uint32)
     counts = np.zeros(max(1, len(pr)), dtype=np.uint64)
-    surv = np.zeros(max(1, cap), dtype=np.uint64)
+    surv = np.empty(max(1, cap), dtype=np.uint64)   # first n_survivors written
     ns, npairs = ctypes.c_uint64(0), ctypes.c_uint64(0)
     st = _load().cuboid_sieve_range(ctx, int(p0), int(p1), int(q0), int(q1), _p(pr, u32), len(pr),
                                     _p(surv, u64), int(cap), ctypes.byref(ns), _p(counts, u64),
@@ -222,7 +222,7 @@ def cuboid_sieve_region(ctx, p0, p1, primes, band_rows=100, cap=1 << 16, stream=
     survivors as (p, q) pairs, r_max per band of band_rows rows)."""
     pr = _arr(primes, np.uint32)
     counts = np.zeros(max(1, len(pr)), dtype=np.uint64)
-    surv = np.zeros(max(1, cap), dtype=np.uint64)
+    surv = np.empty(max(1, cap), dtype=np.uint64)
     n_bands = (int(p1) - int(p0) + band_rows) // band_rows if p1 >= p0 and band_rows else 1
     rmax = np.zeros(max(1, n_bands), dtype=np.uint32)
     ns, npairs = ctypes.c_uint64(0), ctypes.c_uint64(0)
@@ -271,7 +271,7 @@ def cuboid_search_current(h):
 
 
 def cuboid_search_survivors(h, cap=1 << 16):
-    buf = np.zeros(max(1, cap), dtype=np.uint64)
+    buf = np.empty(max(1, cap), dtype=np.uint64)
     n = ctypes.c_uint64(0)
     st = _load().cuboid_search_survivors(h, _p(buf, u64), int(cap), ctypes.byref(n))
     _check(st, "cuboid_search_survivors", needed=n.value if st == E_CAPACITY else None)
@@ -461,7 +461,7 @@ def cuboid_server_poll(srv, ticket, n_primes, cap=1024, wait=True):
     """dict(status, counts, n_pairs, n_survivors, survivors, latency_ns, ...) or
     None when wait is False and the ticket is not finished."""
     counts = np.zeros(max(1, n_primes), dtype=np.uint64)
-    surv = np.zeros(max(1, cap), dtype=np.uint64)
+    surv = np.empty(max(1, cap), dtype=np.uint64)
     res = cuboid_result()
     res.survivors = _p(surv, u64)
     res.cap = int(cap)
