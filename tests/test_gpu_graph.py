@@ -155,3 +155,22 @@ def test_result_arrays_reused_across_calls(pair):
         st_e, fresh = cb.cuboid_sieve_batch(e, rects, primes, caps=128)
         assert st == st_e
         _same_batch(held, fresh)
+
+
+def test_replays_on_a_caller_stream(pair):
+    import torch
+    g, e = pair
+    s = torch.cuda.Stream()
+    primes = wl.PRIMES_C2
+    for seed in range(3):
+        rects = _batch(700 + seed, 62)
+        st_g, out_g = cb.cuboid_sieve_batch(g, rects, primes, caps=64, stream=s)
+        st_e, out_e = cb.cuboid_sieve_batch(e, rects, primes, caps=64)
+        assert st_g == st_e == cb.OK
+        _same_batch(out_g, out_e)
+        # torch work queued on the same stream between replays
+        x = torch.arange(1 << 16, device="cuda")
+        with torch.cuda.stream(s):
+            y = (x * 3).sum()
+        s.synchronize()
+        assert int(y) == 3 * ((1 << 16) - 1) * (1 << 16) // 2

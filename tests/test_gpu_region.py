@@ -128,3 +128,22 @@ def test_section6_scan_matches_the_paper(ctx):
     assert sum(int(c) for c in got["counts"]) == got["n_pairs"]
     # the scanned pairs are a coprime subset of the ~0.7e12 the paper counts
     assert 0.55 * pc["pairs_tested"]["value"] < got["n_pairs"] < pc["pairs_tested"]["value"]
+
+
+def test_section6_scan_against_the_oracle(ctx):
+    """The whole scan of section 6 element by element against the oracle's own
+    run of it (tests/golden/oracle_s6.json, written by make_golden.py s6):
+    per-prime first-rejecter counts, pair count, survivors and r_max for each
+    of the 1540 hundreds of p."""
+    import os
+    path = golden_path("oracle_s6.json")
+    if not os.path.exists(path):
+        pytest.skip("oracle_s6.json not generated")
+    with open(path) as f:
+        g = json.load(f)
+    got = cb.cuboid_sieve_region(ctx, g["p0"], g["p1"], g["primes"], band_rows=g["band_rows"])
+    assert got["n_pairs"] == g["n_pairs"]
+    assert [int(c) for c in got["counts"]] == g["counts"]
+    assert got["n_survivors"] == g["n_survivors"] == 0
+    assert [int(x) for x in got["r_max"]] == g["r_max"]
+    assert g["max_depth_prime"] == 137
