@@ -2,8 +2,10 @@
 (include/cuboid.h).  Argument marshalling only: every step of the sieve runs in
 the library's HIP kernels.  Raises CuboidError for non-zero status codes.
 
-Streams: pass a torch.cuda.Stream, a raw hipStream_t integer, or None (the
-context's own stream).
+Streams: None (the context's own stream) or a raw hipStream_t integer created
+by the HIP runtime the library links (/opt/rocm); torch's default stream maps to
+None, other torch streams are refused (torch wheels carry a HIP runtime of
+their own).
 """
 import ctypes
 import os
@@ -151,11 +153,19 @@ def _p(a, ct):
 
 
 def _stream(stream):
+    """None (the context's stream), or a raw hipStream_t of the HIP runtime the
+    library is linked against.  PyTorch wheels carry their own HIP runtime, so
+    a torch stream other than its default (null) one is not a stream of the
+    library's runtime and is refused."""
     if stream is None:
         return None
     if isinstance(stream, int):
-        return ctypes.c_void_p(stream)
-    return ctypes.c_void_p(int(stream.cuda_stream))
+        return ctypes.c_void_p(stream) if stream else None
+    handle = int(stream.cuda_stream)
+    if handle:
+        raise ValueError("a torch stream belongs to torch's own HIP runtime; pass None or a "
+                         "hipStream_t created by the library's runtime")
+    return None
 
 
 def _check(st, what, needed=None):

@@ -88,7 +88,7 @@ extern "C" int cuboid_autotune(cuboid_ctx *ctx, const uint32_t *primes, uint32_t
     Plan *pl = nullptr;
     st = build_plan(ctx, sorted, &pl);
     if (st) return st;
-    const uint32_t budget = (uint32_t)std::min<size_t>(ctx->max_lds - kSweepFixedLds, 96 * 1024);
+    const uint32_t budget = (uint32_t)(ctx->max_lds - kSweepFixedLds);   // dense tables: all the LDS left
     const uint32_t kmax = default_dense(*pl, budget);
     const uint32_t cus = (uint32_t)ctx->cu_count;
     // sample: 32768 rows x 65536 columns near 2^19 (the scale of the batched

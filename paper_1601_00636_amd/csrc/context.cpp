@@ -172,13 +172,16 @@ int build_plan(cuboid_ctx *ctx, const std::vector<uint32_t> &primes, Plan **out)
     return CUBOID_OK;
 }
 
+// LDS bytes of the dense window table of prime r: r rows of r + kDenseExt words
+uint64_t dense_table_bytes(uint64_t r) { return 8 * r * (r + kDenseExt); }
+
 uint32_t default_dense(const Plan &pl, uint32_t lds_budget) {
     uint64_t bytes = 0;
     uint32_t k = 0;
     while (k < pl.nontriv_idx.size() && k < (uint32_t)kKMax) {
         const uint64_t r = pl.primes[pl.nontriv_idx[k]];
-        if (bytes + 8 * r * r > lds_budget) break;
-        bytes += 8 * r * r;
+        if (bytes + dense_table_bytes(r) > lds_budget) break;
+        bytes += dense_table_bytes(r);
         ++k;
     }
     return k;
@@ -199,12 +202,17 @@ int build_dense(cuboid_ctx *ctx, Plan *pl, uint32_t K, DenseSet **out) {
         const uint32_t i = pl->nontriv_idx[k];
         const uint32_t r = pl->primes[i];
         pr[k] = r; vo[k] = pl->voff[i]; io[k] = pl->ioff[i]; wo[k] = (uint32_t)words;
-        work[k] = (uint64_t)r * r;
+        work[k] = (uint64_t)r * (r + kDenseExt);
         ds->dr[k] = r;
         ds->dm[k] = magic_of(r);
-        ds->dstep[k] = 64 % r;
+        // 64^(r-2) = 64^-1 mod r
+        uint64_t inv = 1, b = 64 % r;
+        for (uint64_t e = r - 2; e; e >>= 1, b = b * b % r)
+            if (e & 1) inv = inv * b % r;
+        ds->dinv[k] = (uint32_t)inv;
+        ds->dext[k] = kDenseExt % r;
         ds->doff[k] = (uint32_t)(words * 8);
-        words += (uint64_t)r * r;
+        words += (uint64_t)r * (r + kDenseExt);
     }
     ds->words = (uint32_t)words;
     HIPCHK(ds->tab.ensure(words * 8));
@@ -273,9 +281,11 @@ cuboid_tuning tuning_for(cuboid_ctx *ctx, const std::vector<uint32_t> &primes, c
     if (it != ctx->tunings.end()) t = it->second;
     else { t.dense_primes = 0xffffffffu; t.workgroups = 0; t.lds_budget = kDefaultLdsBudget; t.reserved = 0; }
     if (t.lds_budget == 0) t.lds_budget = kDefaultLdsBudget;
-    const uint32_t kmax = default_dense(pl, t.lds_budget);
+    // the dense tables and the sweep's fixed LDS must fit one workgroup
+    const uint32_t room = ctx->max_lds > kSweepFixedLds ? (uint32_t)(ctx->max_lds - kSweepFixedLds) : 0;
+    const uint32_t kmax = default_dense(pl, std::min(t.lds_budget, room));
     if (t.dense_primes > kmax) t.dense_primes = kmax;
-    if (t.workgroups == 0) t.workgroups = 2 * ctx->cu_count;
+    if (t.workgroups == 0) t.workgroups = ctx->cu_count;
     return t;
 }
 
@@ -322,7 +332,8 @@ SweepParams sweep_params(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, co
     memset(&P, 0, sizeof(P));
     P.K = ds.K;
     for (uint32_t k = 0; k < ds.K; ++k) {
-        P.dr[k] = ds.dr[k]; P.dm[k] = ds.dm[k]; P.dstep[k] = ds.dstep[k]; P.doff[k] = ds.doff[k];
+        P.dr[k] = ds.dr[k]; P.dm[k] = ds.dm[k]; P.dinv[k] = ds.dinv[k]; P.doff[k] = ds.doff[k];
+        P.dext[k] = ds.dext[k];
     }
     P.dense_words = ds.words;
     P.dense_tab = (const uint64_t *)ds.tab.p;

@@ -8,7 +8,8 @@
 namespace cuboid {
 
 constexpr int kWave = 64;            // CDNA wavefront width
-constexpr int kWavesPerWG = 8;       // sweep workgroup = 512 lanes
+constexpr int kWavesPerWG = 16;      // sweep workgroup = 1024 lanes, one per CU
+constexpr int kDenseExt = 16;        // entries past r in each row of a dense window table
 constexpr int kKMax = 12;            // most dense (bit-window) primes per launch
 constexpr int kMaxBigFactors = 7;    // distinct primes >= 7 of a uint32 (7*11*..*29 < 2^32 < that*31)
 constexpr int kQueueCap = 128;       // per-wave queue of windows that outlive the dense primes
@@ -75,7 +76,8 @@ struct SweepParams {
     uint32_t K;                          // dense primes in this launch
     uint32_t dr[kKMax];                  // dense prime r
     uint32_t dm[kKMax];                  // floor(2^32 / r)
-    uint32_t dstep[kKMax];               // 64 mod r
+    uint32_t dinv[kKMax];                // inverse of 64 modulo r
+    uint32_t dext[kKMax];                // kDenseExt mod r
     uint32_t doff[kKMax];                // LDS byte offset of that prime's window table
     uint32_t dense_words;                // 64-bit words of all window tables
     const uint64_t *dense_tab;           // window tables in HBM (copied to LDS)

@@ -276,12 +276,20 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
         // a window starting above edge_hi reaches past hi_min
         const uint32_t edge_hi = hi_min >= (uint32_t)(kWave - 1) ? hi_min - (kWave - 1) : 0;
 
-        uint32_t lb[KD + 1], ok[KD + 1];
+        // dense prime d: the window starting at column qs (offset o = qs mod
+        // r) is entry k0 = o / 64 mod r of the lane's row, the following ones
+        // k0 + 1, k0 + 2, ...; lb[d] is the lane's byte address of entry kq[d]
+        // and every prime moves on by one entry (8 bytes, kk8) per window;
+        // every kDenseExt windows kq moves on by kDenseExt mod r, kept below r
+        // (entries kq .. kq + kDenseExt - 1 < r + kDenseExt are in the row)
+        uint32_t lb[KD + 1], kq[KD + 1];
 #pragma unroll
         for (int k = 0; k < KD; ++k) {
-            lb[k] = P.doff[k] + modr(p, P.dr[k], P.dm[k]) * P.dr[k] * 8;
-            ok[k] = uni(modr(qs, P.dr[k], P.dm[k]));
+            const uint32_t r = P.dr[k];
+            kq[k] = uni(mulr(modr(qs, r, P.dm[k]), P.dinv[k], r, P.dm[k]));
+            lb[k] = P.doff[k] + (modr(p, r, P.dm[k]) * (r + kDenseExt) + kq[k]) * 8;
         }
+        uint32_t kk8 = 0;
         uint32_t o30 = uni(qs % kWheel);
 
         // factor l of p: fo = distance from the window start to the next
@@ -327,11 +335,23 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
             npairs_hi = __builtin_popcount((uint32_t)(alive >> 32)) + npairs_hi;
 #pragma unroll
             for (int d = 0; d < KD; ++d) {
-                alive &= ~lds64(smem, lb[d] + ok[d] * 8);
+                alive &= ~lds64(smem, lb[d] + kk8);
                 left[d] = __builtin_popcount((uint32_t)alive) + left[d];
                 left_hi[d] = __builtin_popcount((uint32_t)(alive >> 32)) + left_hi[d];
-                ok[d] += P.dstep[d];
-                if (ok[d] >= P.dr[d]) ok[d] -= P.dr[d];
+            }
+            kk8 += 8;
+            if (kk8 == kDenseExt * 8) {
+                kk8 = 0;
+#pragma unroll
+                for (int d = 0; d < KD; ++d) {
+                    kq[d] += P.dext[d];
+                    if (kq[d] >= P.dr[d]) {
+                        kq[d] -= P.dr[d];
+                        lb[d] += (P.dext[d] - P.dr[d]) * 8;
+                    } else {
+                        lb[d] += P.dext[d] * 8;
+                    }
+                }
             }
             o30 += kWave % kWheel;
             if (o30 >= (uint32_t)kWheel) o30 -= kWheel;

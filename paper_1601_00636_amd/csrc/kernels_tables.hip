@@ -129,9 +129,10 @@ __global__ void pack_table_kernel(uint32_t r, const uint8_t *v, const uint16_t *
     }
 }
 
-// Window table of a dense prime r: entry a*r + o holds the 64 bits
-// u_r(a, (o + j) mod r), j = 0..63, so that one 64-bit read answers a whole
-// run of 64 consecutive columns q with q mod r = o for row residue a.
+// Window table of a dense prime r: entry a*(r + kDenseExt) + k holds the 64
+// bits u_r(a, (o + j) mod r), j = 0..63, with o = 64 k mod r, so that one
+// 64-bit read answers a whole run of 64 consecutive columns q with q mod r = o
+// for row residue a, and the next 64 columns are at entry k + 1.
 __global__ void dense_windows_kernel(const uint32_t *pr, const uint32_t *voff,
                                      const uint32_t *ioff, const uint32_t *woff, uint32_t n,
                                      const uint64_t *prefix, uint64_t total, const uint8_t *vpool,
@@ -141,9 +142,12 @@ __global__ void dense_windows_kernel(const uint32_t *pr, const uint32_t *voff,
         const uint32_t i = find_segment(prefix, n, g);
         const uint32_t r = pr[i];
         const uint32_t m = (uint32_t)(0x100000000ull / r);
+        // row a holds r + kDenseExt entries; entry k is the window that
+        // starts at column offset 64 k mod r, so consecutive windows of a row
+        // are consecutive entries
         const uint32_t e = (uint32_t)(g - prefix[i]);
-        uint32_t o;
-        const uint32_t a = divr(e, r, m, &o);
+        const uint32_t a = e / (r + kDenseExt), k = e % (r + kDenseExt);
+        const uint32_t o = (uint32_t)(((uint64_t)k * 64) % r);
         const uint8_t *v = vpool + voff[i];
         const uint16_t *inv = ipool + ioff[i];
         uint64_t w = 0;

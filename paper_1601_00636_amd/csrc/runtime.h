@@ -51,7 +51,8 @@ struct HostBuf {
 // list of the remaining ("deep") primes.
 struct DenseSet {
     uint32_t K = 0;
-    uint32_t dr[kKMax] = {0}, dm[kKMax] = {0}, dstep[kKMax] = {0}, doff[kKMax] = {0};
+    uint32_t dr[kKMax] = {0}, dm[kKMax] = {0}, dinv[kKMax] = {0}, doff[kKMax] = {0};
+    uint32_t dext[kKMax] = {0};
     uint32_t words = 0;
     DevBuf tab;
     uint32_t n_deep = 0;

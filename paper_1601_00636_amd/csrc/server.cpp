@@ -287,7 +287,8 @@ int launch(cuboid_server *S, StreamState &st) {
     const DenseSet &ds = *S->ds;
     P.K = ds.K;
     for (uint32_t k = 0; k < ds.K; ++k) {
-        P.dr[k] = ds.dr[k]; P.dm[k] = ds.dm[k]; P.dstep[k] = ds.dstep[k]; P.doff[k] = ds.doff[k];
+        P.dr[k] = ds.dr[k]; P.dm[k] = ds.dm[k]; P.dinv[k] = ds.dinv[k]; P.doff[k] = ds.doff[k];
+        P.dext[k] = ds.dext[k];
     }
     P.dense_words = ds.words;
     P.dense_tab = (const uint64_t *)ds.tab.p;

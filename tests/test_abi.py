@@ -109,3 +109,15 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, ROOT + "/bench.py", "--gpus", "2"],
                        stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_streams_of_another_runtime_are_refused():
+    class FakeTorchStream:
+        cuda_stream = 0x1234
+    class DefaultTorchStream:
+        cuda_stream = 0
+    assert cb._stream(None) is None and cb._stream(0) is None
+    assert cb._stream(DefaultTorchStream()) is None
+    assert cb._stream(0x5000).value == 0x5000
+    with pytest.raises(ValueError):
+        cb._stream(FakeTorchStream())

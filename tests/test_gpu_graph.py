@@ -158,19 +158,23 @@ def test_result_arrays_reused_across_calls(pair):
 
 
 def test_replays_on_a_caller_stream(pair):
-    import torch
-    g, e = pair
-    s = torch.cuda.Stream()
-    primes = wl.PRIMES_C2
-    for seed in range(3):
-        rects = _batch(700 + seed, 62)
-        st_g, out_g = cb.cuboid_sieve_batch(g, rects, primes, caps=64, stream=s)
-        st_e, out_e = cb.cuboid_sieve_batch(e, rects, primes, caps=64)
-        assert st_g == st_e == cb.OK
-        _same_batch(out_g, out_e)
-        # torch work queued on the same stream between replays
-        x = torch.arange(1 << 16, device="cuda")
-        with torch.cuda.stream(s):
-            y = (x * 3).sum()
-        s.synchronize()
-        assert int(y) == 3 * ((1 << 16) - 1) * (1 << 16) // 2
+    # a stream of the HIP runtime the library links (the loaded libamdhip64)
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    handle = ctypes.c_void_p()
+    assert hip.hipStreamCreate(ctypes.byref(handle)) == 0
+    try:
+        g, e = pair
+        primes = wl.PRIMES_C2
+        for seed in range(3):
+            rects = _batch(700 + seed, 62)
+            st_g, out_g = cb.cuboid_sieve_batch(g, rects, primes, caps=64, stream=handle.value)
+            st_e, out_e = cb.cuboid_sieve_batch(e, rects, primes, caps=64)
+            assert st_g == st_e == cb.OK
+            _same_batch(out_g, out_e)
+            # the context's own work between replays on the caller's stream
+            one = cb.cuboid_sieve_range(g, 3, 900, 7, 1100, primes)
+            assert one["n_pairs"] == cb.cuboid_sieve_range(e, 3, 900, 7, 1100, primes)["n_pairs"]
+    finally:
+        assert hip.hipStreamSynchronize(handle) == 0
+        assert hip.hipStreamDestroy(handle) == 0

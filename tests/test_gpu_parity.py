@@ -142,6 +142,21 @@ def test_edge_rectangles(ctx, rect):
     _cmp(res, ref)
 
 
+@pytest.mark.parametrize("primes", [wl.PRIMES_C2, [11, 13, 17, 19, 23, 29, 31, 37, 41, 43]])
+def test_long_rows(ctx, primes):
+    # few row blocks, a million columns: each wave walks thousands of windows
+    # of the same rows, through every fold-back of the dense tables' offsets
+    rect = (1, 128, 1, 10**6)
+    ref = oracle.sieve(*rect, primes)
+    for k in (0, 5, 10):
+        cb.cuboid_set_tuning(ctx, primes, dense_primes=k, workgroups=4, lds_budget=160 * 1024)
+        try:
+            res = cb.cuboid_sieve_range(ctx, *rect, primes)
+        finally:
+            cb.cuboid_set_tuning(ctx, primes)
+        _cmp(res, ref)
+
+
 @pytest.mark.parametrize("k", [0, 1, 3, 5, 7, 9, 12])
 def test_dense_count_does_not_change_results(ctx, k):
     primes = wl.primes_upto(120, 3)
