@@ -169,6 +169,7 @@ def section6_scan(cb, wl, ctx, stream, torch):
     return {"p_range": [1, 154000], "primes": "11..541 (96)", "band_rows": 100,
             "coprime_pairs": g6["n_pairs"], "survivors": g6["n_survivors"],
             "deepest_prime": int(g6["r_max"].max()), "ms": dt * 1e3, "sweep_ms": t6["sweep_ms"],
+            "tuning": cb.cuboid_get_tuning(ctx, pp),
             "value": g6["n_pairs"] / dt, "paper_hours": 4130 / 60.0}
 
 
@@ -209,7 +210,7 @@ def main():
         return 0
     reqs = wl.batched_requests(4096)
     primes = wl.PRIMES_BATCHED
-    tun = cb.cuboid_autotune(ctx, primes)
+    tun = cb.cuboid_autotune_for(ctx, primes, reqs)
     cb.cuboid_enable_timing(ctx, True)
     _, trivial = cb.cuboid_canonical_primes(primes)
     trivial = np.array([r in (2, 3, 5, 7) for r in primes])
@@ -316,7 +317,7 @@ def main():
                                        "batched_speedup": (tot / dt) and value / (tot / dt)}
         # the plain square 1..1e5 with primes 3..997
         p3 = wl.PRIMES_C3
-        cb.cuboid_autotune(ctx, p3)
+        cb.cuboid_autotune_for(ctx, p3, [(1, 10**5, 1, 10**5)])
         r3 = cb.cuboid_sieve_range(ctx, 1, 10**5, 1, 10**5, p3, stream=stream)
         reps = []
         for _ in range(5):

@@ -305,19 +305,36 @@ int cuboid_server_stop(cuboid_server *srv);
 
 typedef struct cuboid_tuning {
     uint32_t dense_primes;   /* K: leading non-trivial primes tested as 64-wide bit windows */
-    uint32_t workgroups;     /* persistent grid size (0 = two per compute unit) */
-    uint32_t lds_budget;     /* bytes of LDS allowed for the dense windows      */
-    uint32_t reserved;
+    uint32_t workgroups;     /* persistent grid size (0 = one per compute unit) */
+    uint32_t lds_budget;     /* bytes of LDS allowed for the dense windows
+                                (0 = all that a workgroup has left)         */
+    uint32_t schedule;       /* how waves share a launch's units: 0 = by size
+                                (pieces of up to 64 units dealt round-robin below
+                                16384 units per wave, else a shared counter),
+                                1 = round-robin pieces, 2 = shared counter   */
 } cuboid_tuning;
 
 /*
- * Time candidate tunings for `primes` on a sample rectangle and keep the
- * fastest for this context; if cache_path is non-NULL the choice is read from
+ * Time candidate tunings for `primes` (the last five dense-prime counts that
+ * fit in LDS, times grids of 1, 2, 4 and 8 workgroups per compute unit) on a
+ * sample rectangle of 32768 x 65536 pairs near 2^19 and keep the fastest for
+ * this context; if cache_path is non-NULL the choice is read from
  * / appended to that JSON-lines file, keyed by device architecture and prime
  * set.  Results never depend on the tuning.  out may be NULL.
  */
 int cuboid_autotune(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes,
                     const char *cache_path, cuboid_tuning *out);
+
+/*
+ * As cuboid_autotune, but timed on the caller's own requests: a batch that
+ * stands for the workload to come (the same rectangles as cuboid_sieve_batch
+ * takes; the sample is swept several times per candidate, so a few tens of
+ * milliseconds of work is plenty).  The cache key adds a hash of the sample.
+ * Errors: E_ARG (no sample), E_RANGE (a rectangle is invalid), E_PRIMES.
+ */
+int cuboid_autotune_for(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes,
+                        const cuboid_request *sample, uint32_t n_sample,
+                        const char *cache_path, cuboid_tuning *out);
 
 /* Set (NULL = restore defaults) or read the tuning used for `primes`. */
 int cuboid_set_tuning(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes,

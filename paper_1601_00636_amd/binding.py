@@ -36,7 +36,7 @@ class cuboid_result(ctypes.Structure):
 
 
 class cuboid_tuning(ctypes.Structure):
-    _fields_ = [("dense_primes", u32), ("workgroups", u32), ("lds_budget", u32), ("reserved", u32)]
+    _fields_ = [("dense_primes", u32), ("workgroups", u32), ("lds_budget", u32), ("schedule", u32)]
 
 
 class cuboid_timing(ctypes.Structure):
@@ -104,6 +104,8 @@ def _load():
         "cuboid_canonical_primes": ([P(u32), u32, P(u32), P(u8)], i32),
         "cuboid_sieve_batch": ([vp, P(cuboid_request), u32, P(u32), u32, P(cuboid_result), vp], i32),
         "cuboid_autotune": ([vp, P(u32), u32, ctypes.c_char_p, P(cuboid_tuning)], i32),
+        "cuboid_autotune_for": ([vp, P(u32), u32, P(cuboid_request), u32, ctypes.c_char_p,
+                                 P(cuboid_tuning)], i32),
         "cuboid_set_tuning": ([vp, P(u32), u32, P(cuboid_tuning)], i32),
         "cuboid_get_tuning": ([vp, P(u32), u32, P(cuboid_tuning)], i32),
         "cuboid_enable_timing": ([vp, i32], i32),
@@ -420,13 +422,15 @@ def cuboid_enable_graphs(ctx, on=True):
     _check(_load().cuboid_enable_graphs(ctx, 1 if on else 0), "cuboid_enable_graphs")
 
 
-def cuboid_set_tuning(ctx, primes, dense_primes=None, workgroups=0, lds_budget=0):
+def cuboid_set_tuning(ctx, primes, dense_primes=None, workgroups=0, lds_budget=0, schedule=0):
+    """No keyword arguments: back to the defaults.  schedule: 0 by size,
+    1 round-robin pieces, 2 shared counter."""
     pr = _arr(primes, np.uint32)
-    if dense_primes is None and not workgroups and not lds_budget:
+    if dense_primes is None and not workgroups and not lds_budget and not schedule:
         _check(_load().cuboid_set_tuning(ctx, _p(pr, u32), len(pr), None), "cuboid_set_tuning")
         return
     t = cuboid_tuning(0xffffffff if dense_primes is None else int(dense_primes), int(workgroups),
-                      int(lds_budget), 0)
+                      int(lds_budget), int(schedule))
     _check(_load().cuboid_set_tuning(ctx, _p(pr, u32), len(pr), ctypes.byref(t)),
            "cuboid_set_tuning")
 
@@ -436,7 +440,8 @@ def cuboid_get_tuning(ctx, primes):
     t = cuboid_tuning()
     _check(_load().cuboid_get_tuning(ctx, _p(pr, u32), len(pr), ctypes.byref(t)),
            "cuboid_get_tuning")
-    return dict(dense_primes=t.dense_primes, workgroups=t.workgroups, lds_budget=t.lds_budget)
+    return dict(dense_primes=t.dense_primes, workgroups=t.workgroups, lds_budget=t.lds_budget,
+                schedule=t.schedule)
 
 
 def cuboid_autotune(ctx, primes, cache_path=None):
@@ -445,7 +450,21 @@ def cuboid_autotune(ctx, primes, cache_path=None):
     cp = cache_path.encode() if cache_path else None
     _check(_load().cuboid_autotune(ctx, _p(pr, u32), len(pr), cp, ctypes.byref(t)),
            "cuboid_autotune")
-    return dict(dense_primes=t.dense_primes, workgroups=t.workgroups, lds_budget=t.lds_budget)
+    return dict(dense_primes=t.dense_primes, workgroups=t.workgroups, lds_budget=t.lds_budget,
+                schedule=t.schedule)
+
+
+def cuboid_autotune_for(ctx, primes, sample, cache_path=None):
+    """sample: (n, 4) array-like of (p0, p1, q0, q1), requests standing for the workload."""
+    pr = _arr(primes, np.uint32)
+    reqa = np.ascontiguousarray(np.asarray(sample, dtype=np.uint32).reshape(-1, 4))
+    t = cuboid_tuning()
+    cp = cache_path.encode() if cache_path else None
+    _check(_load().cuboid_autotune_for(ctx, _p(pr, u32), len(pr),
+                                       reqa.ctypes.data_as(P(cuboid_request)), reqa.shape[0], cp,
+                                       ctypes.byref(t)), "cuboid_autotune_for")
+    return dict(dense_primes=t.dense_primes, workgroups=t.workgroups, lds_budget=t.lds_budget,
+                schedule=t.schedule)
 
 
 def cuboid_server_start(ctx, primes, streams=0, max_slots=0, max_launch_units=0,

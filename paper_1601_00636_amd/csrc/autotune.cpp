@@ -50,7 +50,7 @@ bool read_cache(const char *path, const std::string &arch, const std::string &ke
         out->dense_primes = k;
         out->workgroups = w;
         out->lds_budget = b;
-        out->reserved = 0;
+        out->schedule = 0;
         found = true;   // the last matching line wins
     }
     fclose(f);
@@ -68,17 +68,12 @@ void append_cache(const char *path, const std::string &arch, const std::string &
     fclose(f);
 }
 
-}  // namespace
-
-extern "C" int cuboid_autotune(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes,
-                               const char *cache_path, cuboid_tuning *out) {
-    if (!ctx_is_live(ctx)) return CUBOID_E_NOT_LOADED;
-    std::vector<uint32_t> sorted;
-    int st = canonical_primes(primes, n_primes, &sorted);
-    if (st) return st;
-    CtxLock g(ctx);
-    if (hipSetDevice(ctx->device) != hipSuccess) return CUBOID_E_DEVICE;
-    const std::string arch(ctx->arch), key = prime_key(sorted);
+// Times every candidate on the sample and keeps the fastest.  A sample that
+// overflows the survivor scratch still times the whole sweep, so E_LIMIT and
+// E_CAPACITY count as a completed run.
+int tune(cuboid_ctx *ctx, const std::vector<uint32_t> &sorted, const cuboid_request *sample,
+         uint32_t n_sample, const std::string &key, const char *cache_path, cuboid_tuning *out) {
+    const std::string arch(ctx->arch);
     cuboid_tuning best;
     if (cache_path && read_cache(cache_path, arch, key, &best)) {
         ctx->tunings[sorted] = best;
@@ -86,32 +81,29 @@ extern "C" int cuboid_autotune(cuboid_ctx *ctx, const uint32_t *primes, uint32_t
         return CUBOID_OK;
     }
     Plan *pl = nullptr;
-    st = build_plan(ctx, sorted, &pl);
+    int st = build_plan(ctx, sorted, &pl);
     if (st) return st;
     const uint32_t budget = (uint32_t)(ctx->max_lds - kSweepFixedLds);   // dense tables: all the LDS left
     const uint32_t kmax = default_dense(*pl, budget);
     const uint32_t cus = (uint32_t)ctx->cu_count;
-    // sample: 32768 rows x 65536 columns near 2^19 (the scale of the batched
-    // workloads), about 2^19 units: enough work per wave for the timing to
-    // reflect a full launch
-    std::vector<cuboid_request> rect(1);
-    rect[0].p0 = 1u << 19; rect[0].p1 = (1u << 19) + 32767;
-    rect[0].q0 = 1u << 19; rect[0].q1 = (1u << 19) + 65535;
     const bool saved_timing = ctx->timing;
     ctx->timing = true;
     double best_ms = 1e30;
-    best.dense_primes = 0; best.workgroups = 2 * cus; best.lds_budget = budget; best.reserved = 0;
+    best.dense_primes = 0; best.workgroups = cus; best.lds_budget = budget; best.schedule = 0;
     const uint32_t klo = kmax > 5 ? kmax - 5 : 0;
-    const uint32_t wgs[4] = {cus, 2 * cus, 3 * cus, 4 * cus};
+    // one workgroup fills a compute unit's LDS, so grids beyond the CU count
+    // run as successive waves of workgroups: smaller pieces that even out
+    // the finishing times of unequal units
+    const uint32_t wgs[4] = {cus, 2 * cus, 4 * cus, 8 * cus};
     for (uint32_t K = klo; K <= kmax; ++K) {
         for (uint32_t w : wgs) {
             cuboid_tuning t;
-            t.dense_primes = K; t.workgroups = w; t.lds_budget = budget; t.reserved = 0;
+            t.dense_primes = K; t.workgroups = w; t.lds_budget = budget; t.schedule = 0;
             ctx->tunings[sorted] = t;
             double ms_best = 1e30;
             for (int rep = 0; rep < 3; ++rep) {
-                st = sieve_rects(ctx, sorted, rect.data(), (uint32_t)rect.size(), 1 << 16,
-                                 ctx->stream, &ctx->h_out);
+                st = sieve_rects(ctx, sorted, sample, n_sample, 1 << 16, ctx->stream, &ctx->h_out);
+                if (st == CUBOID_E_LIMIT || st == CUBOID_E_CAPACITY) st = CUBOID_OK;
                 if (st) break;
                 ms_best = std::min(ms_best, ctx->last.sweep_ms);
             }
@@ -129,4 +121,55 @@ extern "C" int cuboid_autotune(cuboid_ctx *ctx, const uint32_t *primes, uint32_t
     if (cache_path) append_cache(cache_path, arch, key, best, best_ms);
     if (out) *out = best;
     return CUBOID_OK;
+}
+
+uint64_t sample_hash(const cuboid_request *r, uint32_t n) {
+    uint64_t h = 1469598103934665603ull;
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint32_t v[4] = {r[i].p0, r[i].p1, r[i].q0, r[i].q1};
+        for (uint32_t x : v)
+            for (int b = 0; b < 4; ++b) {
+                h ^= (x >> (8 * b)) & 0xff;
+                h *= 1099511628211ull;
+            }
+    }
+    return h;
+}
+
+}  // namespace
+
+extern "C" int cuboid_autotune(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes,
+                               const char *cache_path, cuboid_tuning *out) {
+    if (!ctx_is_live(ctx)) return CUBOID_E_NOT_LOADED;
+    std::vector<uint32_t> sorted;
+    int st = canonical_primes(primes, n_primes, &sorted);
+    if (st) return st;
+    CtxLock g(ctx);
+    if (hipSetDevice(ctx->device) != hipSuccess) return CUBOID_E_DEVICE;
+    // sample: 32768 rows x 65536 columns near 2^19 (the scale of the batched
+    // workloads), about 2^19 units: enough work per wave for the timing to
+    // reflect a full launch
+    cuboid_request rect;
+    rect.p0 = 1u << 19; rect.p1 = (1u << 19) + 32767;
+    rect.q0 = 1u << 19; rect.q1 = (1u << 19) + 65535;
+    return tune(ctx, sorted, &rect, 1, prime_key(sorted), cache_path, out);
+}
+
+extern "C" int cuboid_autotune_for(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes,
+                                   const cuboid_request *sample, uint32_t n_sample,
+                                   const char *cache_path, cuboid_tuning *out) {
+    if (!ctx_is_live(ctx)) return CUBOID_E_NOT_LOADED;
+    if (!sample || n_sample == 0 || n_sample == 0xffffffffu) return CUBOID_E_ARG;
+    for (uint32_t i = 0; i < n_sample; ++i)
+        if (rect_valid(sample[i].p0, sample[i].p1, sample[i].q0, sample[i].q1))
+            return CUBOID_E_RANGE;
+    std::vector<uint32_t> sorted;
+    int st = canonical_primes(primes, n_primes, &sorted);
+    if (st) return st;
+    CtxLock g(ctx);
+    if (hipSetDevice(ctx->device) != hipSuccess) return CUBOID_E_DEVICE;
+    char w[40];
+    snprintf(w, sizeof(w), "_w%u_%016llx", n_sample,
+             (unsigned long long)sample_hash(sample, n_sample));
+    return tune(ctx, sorted, sample, n_sample, prime_key(sorted) + w, cache_path, out);
 }

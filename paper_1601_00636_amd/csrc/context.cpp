@@ -279,12 +279,15 @@ cuboid_tuning tuning_for(cuboid_ctx *ctx, const std::vector<uint32_t> &primes, c
     cuboid_tuning t;
     auto it = ctx->tunings.find(primes);
     if (it != ctx->tunings.end()) t = it->second;
-    else { t.dense_primes = 0xffffffffu; t.workgroups = 0; t.lds_budget = kDefaultLdsBudget; t.reserved = 0; }
-    if (t.lds_budget == 0) t.lds_budget = kDefaultLdsBudget;
-    // the dense tables and the sweep's fixed LDS must fit one workgroup
+    else { t.dense_primes = 0xffffffffu; t.workgroups = 0; t.lds_budget = 0; t.schedule = 0; }
+    // the dense tables and the sweep's fixed LDS must fit one workgroup; by
+    // default the tables take all of the LDS left
     const uint32_t room = ctx->max_lds > kSweepFixedLds ? (uint32_t)(ctx->max_lds - kSweepFixedLds) : 0;
-    const uint32_t kmax = default_dense(pl, std::min(t.lds_budget, room));
+    if (t.lds_budget == 0 || t.lds_budget > room) t.lds_budget = room;
+    const uint32_t kmax = default_dense(pl, t.lds_budget);
     if (t.dense_primes > kmax) t.dense_primes = kmax;
+    // one workgroup per compute unit: waves take their units from a shared
+    // counter, so more workgroups would only load the tables again
     if (t.workgroups == 0) t.workgroups = ctx->cu_count;
     return t;
 }
@@ -355,6 +358,7 @@ SweepParams sweep_params(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, co
     P.surv = (SurvEntry *)ctx->surv.p;
     P.surv_cap = surv_cap;
     P.surv_n = (unsigned long long *)ctx->surv_n.p;
+    P.claim = (unsigned long long *)ctx->surv_n.p + 1;
     return P;
 }
 
@@ -389,10 +393,14 @@ int launch_reqs(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboi
                                   (const uint64_t *)ctx->chunk_prefix.p, sh.n_chunks,
                                   (const uint64_t *)ctx->row_prefix.p, (uint32_t *)ctx->order.p, s));
     }
-    const SweepParams P =
+    SweepParams P =
         sweep_params(ctx, pl, ds, (const ReqDesc *)ctx->reqbuf.p, n, sh.units, surv_cap);
+    P.schedule = tun.schedule;
     const size_t lds = (size_t)ds.words * 8 + kSweepFixedLds;
     if (lds > ctx->max_lds) return CUBOID_E_LIMIT;
+    // a call may launch once per row window: each launch hands out its units
+    // from a fresh claim counter
+    HIPCHK(launch_fill_u64((uint64_t *)P.claim, 1, 0, s));
     if (ctx->timing) HIPCHK(hipEventRecord(ctx->ev_sweep0, s));
     HIPCHK(launch_sweep(P, (int)tun.workgroups, lds, sh.max_p, s));
     if (ctx->timing) HIPCHK(hipEventRecord(ctx->ev_sweep1, s));
@@ -410,7 +418,7 @@ int ensure_scratch(cuboid_ctx *ctx, uint32_t n_req, uint32_t nc, uint64_t surv_c
     ctx->rep_stride_pairs = n_req;
     HIPCHK(ctx->counts.ensure((size_t)rep * n_req * nc * 8 + 8));
     HIPCHK(ctx->pairs.ensure((size_t)rep * n_req * 8 + 8));
-    HIPCHK(ctx->surv_n.ensure(8));
+    HIPCHK(ctx->surv_n.ensure(16));   // survivor count, claim counter
     const uint64_t rounded = (surv_cap + 1023) / 1024 * 1024;
     HIPCHK(ctx->surv.ensure(rounded * sizeof(SurvEntry) + sizeof(SurvEntry)));
     HIPCHK(ctx->surv_tmp.ensure(rounded * sizeof(SurvEntry) + sizeof(SurvEntry)));

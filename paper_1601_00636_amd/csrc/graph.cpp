@@ -90,7 +90,7 @@ hipError_t build_graph(cuboid_ctx *ctx, const GraphArgs &a, hipStream_t s, Batch
         hipError_t r = hipMemcpyAsync(a.block, a.stage, a.L.bytes, hipMemcpyHostToDevice, s);
         if (r == hipSuccess) r = launch_fill_u64((uint64_t *)ctx->counts.p, (uint64_t)ctx->n_rep * ncount, 0, s);
         if (r == hipSuccess) r = launch_fill_u64((uint64_t *)ctx->pairs.p, (uint64_t)ctx->n_rep * ns, 0, s);
-        if (r == hipSuccess) r = launch_fill_u64((uint64_t *)ctx->surv_n.p, 1, 0, s);
+        if (r == hipSuccess) r = launch_fill_u64((uint64_t *)ctx->surv_n.p, 2, 0, s);
         if (r == hipSuccess)
             r = launch_bucket_rows((const ReqDesc *)(a.block + a.L.o_desc), n,
                                    (const uint64_t *)(a.block + a.L.o_cpre), 0,
@@ -228,6 +228,7 @@ int run_batch_graph(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const c
     a.max_p = sh.max_p;
     a.timing = ctx->timing;
     a.P = sweep_params(ctx, pl, ds, (const ReqDesc *)(a.block + L.o_desc), n, 0, surv_cap);
+    a.P.schedule = tun.schedule;
     a.P.units_dev = (const unsigned long long *)a.block;
 
     std::vector<unsigned char> key;

@@ -90,7 +90,7 @@ struct SweepParams {
     const uint16_t *ipool;               // inverse tables
     const ReqDesc *req;
     uint32_t n_req;
-    uint32_t pad0;
+    uint32_t schedule;                   // 0 by size, 1 round-robin pieces, 2 shared counter
     uint64_t n_units;
     unsigned long long *counts;          // [n_rep][slot][nc], canonical ascending order
     unsigned long long *pairs;           // [n_rep][slot]
@@ -102,6 +102,7 @@ struct SweepParams {
     unsigned long long surv_cap;
     unsigned long long *surv_n;
     const unsigned long long *units_dev; // if set, the unit count is read here, not n_units
+    unsigned long long *claim;           // units handed out so far (zero before each launch)
 };
 
 // LDS bytes the sweep needs beyond the dense tables.

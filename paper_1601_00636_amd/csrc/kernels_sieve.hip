@@ -128,6 +128,9 @@ __device__ __forceinline__ uint64_t lds64(const unsigned char *base, uint32_t by
 }
 
 constexpr uint32_t kFlushWindows = 1u << 19;   // per-lane u32 counters stay below 2^31
+constexpr uint64_t kMinClaim = 16;             // smallest piece taken from the shared counter
+constexpr uint64_t kPiece = 64;                // largest round-robin piece
+constexpr uint64_t kGuidedUnitsPerWave = 16384;  // the shared counter from this many units per wave
 
 // KD dense primes; MF factor slots (enough for every row of the launch)
 template <int KD, int MF>
@@ -153,24 +156,10 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
     const uint64_t nwaves = (uint64_t)gridDim.x * kWavesPerWG;
     const uint64_t w = (uint64_t)blockIdx.x * kWavesPerWG + wv;
     const uint64_t n_units = P.units_dev ? uni64(*P.units_dev) : P.n_units;
-    const uint64_t qd = n_units / nwaves, rd = n_units % nwaves;
-    uint64_t u = uni64(qd * w + (rd * w) / nwaves);
-    const uint64_t uend = uni64(qd * (w + 1) + (rd * (w + 1)) / nwaves);
-    if (u >= uend) return;
     const uint32_t rep = uni((uint32_t)(w & (P.n_rep - 1)));
     unsigned long long *cnt_rep = P.counts + (uint64_t)rep * P.rep_stride_counts;
     unsigned long long *pairs_rep = P.pairs + (uint64_t)rep * P.rep_stride_pairs;
-
-    // request holding unit u: last i with req[i].unit0 <= u
-    uint32_t ri;
-    {
-        uint32_t lo = 0, hi = P.n_req;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (uni64(P.req[mid].unit0) <= u) lo = mid; else hi = mid;
-        }
-        ri = uni(lo);
-    }
+    uint32_t ri = 0;   // request holding the current unit
 
     uint32_t left[KD + 1], left_hi[KD + 1];
     for (int k = 0; k <= KD; ++k) { left[k] = 0; left_hi[k] = 0; }
@@ -215,163 +204,229 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
         since_flush = 0;
     };
 
-    while (u < uend) {
-        ReqDesc R = P.req[ri];
+    // The wave's counters hold counts of request R = req[ri] only: they are
+    // flushed when the wave moves on to another request, every kFlushWindows
+    // windows, and once at the end.
+    ReqDesc R;
+    uint32_t held = 0;   // R loaded (wave-uniform)
+    auto load = [&](uint32_t i) {
+        R = P.req[i];
         R.p0 = uni(R.p0); R.p1 = uni(R.p1); R.q0 = uni(R.q0); R.q1 = uni(R.q1);
         R.nrb = uni(R.nrb); R.nwin = uni(R.nwin); R.unit0 = uni64(R.unit0);
         R.rows_p0 = uni(R.rows_p0); R.ip0 = uni(R.ip0);
         R.ulo = uni64(R.ulo); R.ucount = uni64(R.ucount); R.slot = uni(R.slot);
         R.flags = uni(R.flags);
-        const uint64_t rend = R.unit0 + R.ucount;
-        if (u >= rend) {
-            flush(R);
-            ri = uni(ri + 1);
-            continue;
-        }
-        const uint64_t local = u - R.unit0 + R.ulo;
-        const uint32_t rb = uni((uint32_t)(local / R.nwin));
-        const uint32_t win0 = uni((uint32_t)(local % R.nwin));
-        uint64_t seg_end = R.unit0 + ((uint64_t)(rb + 1) * R.nwin - R.ulo);
-        if (seg_end > rend) seg_end = rend;
-        if (seg_end > uend) seg_end = uend;
-        uint32_t nw = uni((uint32_t)(seg_end - u));
-        if (nw > kFlushWindows - since_flush) nw = uni(kFlushWindows - since_flush);
+        held = 1;
+    };
 
-        // ---- segment setup: 64 rows (one per lane), starting column qs ----
-        const uint64_t nrows = (uint64_t)R.p1 - R.p0 + 1;
-        const uint64_t ridx = (uint64_t)rb * kWave + lane;
-        const bool valid = ridx < nrows;
-        uint32_t p = 0;
-        RowInfo rinfo;
-        rinfo.meta = kIdleSubset;
-        for (int f = 0; f < kMaxBigFactors; ++f) rinfo.f[f] = 0;
-        if (valid) {
-            p = R.order ? R.order[ridx] : R.p0 + (uint32_t)ridx;
-            // a row order holds only rows of this request; anything else
-            // leaves the lane idle rather than indexing outside the row table
-            if (p < R.p0 || p > R.p1) {
-                p = 0;
-            } else {
-                rinfo = R.rows[p - R.rows_p0];
-                rinfo.meta &= ~8u;
+    // How the waves share the units.  Round-robin: wave w takes pieces w,
+    // w + nwaves, w + 2 nwaves, ... of up to kPiece units, so every wave samples
+    // the whole launch (rows come grouped by cost) and no shared state is
+    // touched.  Shared counter: pieces of half the remaining units' even
+    // share per wave, never fewer than kMinClaim (guided self-scheduling);
+    // a wave that drew cheap units comes back for more, so all waves finish
+    // within about one small piece of each other.  The counter's atomics
+    // serialise, so it pays only once waves hold many units each.
+    const bool guided =
+        P.schedule == 2 || (P.schedule == 0 && n_units >= nwaves * kGuidedUnitsPerWave);
+    // a small launch deals smaller pieces, so that every wave gets some
+    const uint64_t per_wave = n_units / nwaves;
+    const uint64_t psize = per_wave < 1 ? 1 : (per_wave < kPiece ? per_wave : kPiece);
+    uint64_t piece = w;
+    for (;;) {
+        uint64_t u, uend;
+        if (guided) {
+            uint64_t start = 0, take = 0;
+            if (lane == 0) {
+                const uint64_t seen = __hip_atomic_load(P.claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                take = (seen < n_units ? n_units - seen : 0) / (2 * nwaves);
+                if (take < kMinClaim) take = kMinClaim;
+                start = atomicAdd(P.claim, (unsigned long long)take);
             }
+            u = uni64(start);
+            take = uni64(take);
+            if (u >= n_units) break;
+            uend = n_units - u < take ? n_units : u + take;
+        } else {
+            u = piece * psize;
+            if (u >= n_units) break;
+            uend = n_units - u < psize ? n_units : u + psize;
+            piece += nwaves;
         }
-        const uint32_t nf = (rinfo.meta >> 4) & 15;
-        const uint32_t nfmax = uni(wave_max(nf));
-        const uint32_t wheel_lane = wheel_byte + (rinfo.meta & 15) * (kWheel * 8);
-        const uint32_t qs = R.q0 + win0 * kWave;
-        // columns of this lane's row: [q0, q1], cut to region (1.2) in a
-        // region; only windows reaching past the wave's tightest bounds need
-        // per-lane masks (idle lanes keep the request's bounds: their wheel
-        // row already clears every column)
-        uint32_t rlo = R.q0, rhi = R.q1;
-        if ((R.flags & kReqRegion) && p) {
-            const uint32_t a = region_qmin(p), b = 59u * p;
-            rlo = a > rlo ? a : rlo;
-            rhi = b < rhi ? b : rhi;
-        }
-        if (p == 1 && rlo < 2) rlo = 2;   // (1, 1) is coprime but p = q
-        const uint32_t lo_max = uni(wave_max(rlo));
-        const uint32_t hi_min = uni(wave_min(rhi));
-        // a window starting above edge_hi reaches past hi_min
-        const uint32_t edge_hi = hi_min >= (uint32_t)(kWave - 1) ? hi_min - (kWave - 1) : 0;
-
-        // dense prime d: the window starting at column qs (offset o = qs mod
-        // r) is entry k0 = o / 64 mod r of the lane's row, the following ones
-        // k0 + 1, k0 + 2, ...; lb[d] is the lane's byte address of entry kq[d]
-        // and every prime moves on by one entry (8 bytes, kk8) per window;
-        // every kDenseExt windows kq moves on by kDenseExt mod r, kept below r
-        // (entries kq .. kq + kDenseExt - 1 < r + kDenseExt are in the row)
-        uint32_t lb[KD + 1], kq[KD + 1];
-#pragma unroll
-        for (int k = 0; k < KD; ++k) {
-            const uint32_t r = P.dr[k];
-            kq[k] = uni(mulr(modr(qs, r, P.dm[k]), P.dinv[k], r, P.dm[k]));
-            lb[k] = P.doff[k] + (modr(p, r, P.dm[k]) * (r + kDenseExt) + kq[k]) * 8;
-        }
-        uint32_t kk8 = 0;
-        uint32_t o30 = uni(qs % kWheel);
-
-        // factor l of p: fo = distance from the window start to the next
-        // multiple of l, fd = 64 mod l (64 for l >= 64), fb = LDS byte
-        // offset of its pattern entries
-        uint32_t fo[MF], fd[MF], fl[MF], fb[MF];
-#pragma unroll
-        for (int f = 0; f < MF; ++f) {
-            fl[f] = 0; fd[f] = 0; fo[f] = 0xffffffffu;
-            fb[f] = pat_byte + kPatSmall * 8;
-            if ((uint32_t)f < nfmax && (uint32_t)f < nf) {
-                const uint32_t l = rinfo.f[f];
-                const uint32_t rem = mod_var(qs, l);
-                fl[f] = l;
-                fo[f] = rem ? l - rem : 0;
-                fd[f] = l > (uint32_t)kWave ? (uint32_t)kWave : (uint32_t)kWave % l;
-                if (l < (uint32_t)kWave) fb[f] = pat_byte + c_pat_off[l] * 8;
+        // request holding unit u: the last i with req[i].unit0 <= u, at or after
+        // ri since a wave's pieces only move forward (gallop, then bisect)
+        {
+            uint32_t lo = ri, step = 1;
+            while (lo + step < P.n_req && uni64(P.req[lo + step].unit0) <= u) {
+                lo += step;
+                step <<= 1;
             }
+            uint32_t hi = lo + step < P.n_req ? lo + step : P.n_req;
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (uni64(P.req[mid].unit0) <= u) lo = mid; else hi = mid;
+            }
+            lo = uni(lo);
+            if (held && lo != ri) flush(R);
+            ri = lo;
+            load(ri);
         }
+        while (u < uend) {
+            const uint64_t rend = R.unit0 + R.ucount;
+            if (u >= rend) {
+                flush(R);
+                ri = uni(ri + 1);
+                load(ri);
+                continue;
+            }
+            const uint64_t local = u - R.unit0 + R.ulo;
+            const uint32_t rb = uni((uint32_t)(local / R.nwin));
+            const uint32_t win0 = uni((uint32_t)(local % R.nwin));
+            uint64_t seg_end = R.unit0 + ((uint64_t)(rb + 1) * R.nwin - R.ulo);
+            if (seg_end > rend) seg_end = rend;
+            if (seg_end > uend) seg_end = uend;
+            uint32_t nw = uni((uint32_t)(seg_end - u));
+            if (nw > kFlushWindows - since_flush) nw = uni(kFlushWindows - since_flush);
 
-        // ---- windows ----
-        for (uint32_t k = 0; k < nw; ++k) {
-            const uint32_t qb = qs + k * kWave;
-            uint64_t nc = lds64(smem, wheel_lane + o30 * 8);
-#pragma unroll
-            for (int f = 0; f < MF; ++f) {
-                if ((uint32_t)f < nfmax) {
-                    const uint32_t idx = fo[f] < (uint32_t)kWave ? fo[f] : (uint32_t)kWave;
-                    nc |= lds64(smem, fb[f] + idx * 8);
-                    const uint32_t t = fo[f] - fd[f];
-                    const uint32_t t2 = t + fl[f];
-                    fo[f] = t < t2 ? t : t2;
+            // ---- segment setup: 64 rows (one per lane), starting column qs ----
+            const uint64_t nrows = (uint64_t)R.p1 - R.p0 + 1;
+            const uint64_t ridx = (uint64_t)rb * kWave + lane;
+            const bool valid = ridx < nrows;
+            uint32_t p = 0;
+            RowInfo rinfo;
+            rinfo.meta = kIdleSubset;
+            for (int f = 0; f < kMaxBigFactors; ++f) rinfo.f[f] = 0;
+            if (valid) {
+                p = R.order ? R.order[ridx] : R.p0 + (uint32_t)ridx;
+                // a row order holds only rows of this request; anything else
+                // leaves the lane idle rather than indexing outside the row table
+                if (p < R.p0 || p > R.p1) {
+                    p = 0;
+                } else {
+                    rinfo = R.rows[p - R.rows_p0];
+                    rinfo.meta &= ~8u;
                 }
             }
-            uint64_t alive = ~nc;
-            if (qb < lo_max || qb > edge_hi) {
-                const uint32_t below = rlo > qb ? rlo - qb : 0;
-                const uint32_t upto = rhi >= qb ? rhi - qb + 1 : 0;
-                alive &= (upto < (uint32_t)kWave ? (1ull << upto) - 1 : ~0ull) &
-                         (below < (uint32_t)kWave ? ~0ull << below : 0ull);
+            const uint32_t nf = (rinfo.meta >> 4) & 15;
+            const uint32_t nfmax = uni(wave_max(nf));
+            const uint32_t wheel_lane = wheel_byte + (rinfo.meta & 15) * (kWheel * 8);
+            const uint32_t qs = R.q0 + win0 * kWave;
+            // columns of this lane's row: [q0, q1], cut to region (1.2) in a
+            // region; only windows reaching past the wave's tightest bounds need
+            // per-lane masks (idle lanes keep the request's bounds: their wheel
+            // row already clears every column)
+            uint32_t rlo = R.q0, rhi = R.q1;
+            if ((R.flags & kReqRegion) && p) {
+                const uint32_t a = region_qmin(p), b = 59u * p;
+                rlo = a > rlo ? a : rlo;
+                rhi = b < rhi ? b : rhi;
             }
-            npairs = __builtin_popcount((uint32_t)alive) + npairs;
-            npairs_hi = __builtin_popcount((uint32_t)(alive >> 32)) + npairs_hi;
-#pragma unroll
-            for (int d = 0; d < KD; ++d) {
-                alive &= ~lds64(smem, lb[d] + kk8);
-                left[d] = __builtin_popcount((uint32_t)alive) + left[d];
-                left_hi[d] = __builtin_popcount((uint32_t)(alive >> 32)) + left_hi[d];
+            if (p == 1 && rlo < 2) rlo = 2;   // (1, 1) is coprime but p = q
+            const uint32_t lo_max = uni(wave_max(rlo));
+            const uint32_t hi_min = uni(wave_min(rhi));
+            // a window starting above edge_hi reaches past hi_min
+            const uint32_t edge_hi = hi_min >= (uint32_t)(kWave - 1) ? hi_min - (kWave - 1) : 0;
+
+            // dense prime d: the window starting at column qs (offset o = qs mod
+            // r) is entry k0 = o / 64 mod r of the lane's row, the following ones
+            // k0 + 1, k0 + 2, ...; lb[d] is the lane's byte address of entry kq[d]
+            // and every prime moves on by one entry (8 bytes, kk8) per window;
+            // every kDenseExt windows kq moves on by kDenseExt mod r, kept below r
+            // (entries kq .. kq + kDenseExt - 1 < r + kDenseExt are in the row)
+            uint32_t lb[KD + 1], kq[KD + 1];
+    #pragma unroll
+            for (int k = 0; k < KD; ++k) {
+                const uint32_t r = P.dr[k];
+                kq[k] = uni(mulr(modr(qs, r, P.dm[k]), P.dinv[k], r, P.dm[k]));
+                lb[k] = P.doff[k] + (modr(p, r, P.dm[k]) * (r + kDenseExt) + kq[k]) * 8;
             }
-            kk8 += 8;
-            if (kk8 == kDenseExt * 8) {
-                kk8 = 0;
-#pragma unroll
-                for (int d = 0; d < KD; ++d) {
-                    kq[d] += P.dext[d];
-                    if (kq[d] >= P.dr[d]) {
-                        kq[d] -= P.dr[d];
-                        lb[d] += (P.dext[d] - P.dr[d]) * 8;
-                    } else {
-                        lb[d] += P.dext[d] * 8;
+            uint32_t kk8 = 0;
+            uint32_t o30 = uni(qs % kWheel);
+
+            // factor l of p: fo = distance from the window start to the next
+            // multiple of l, fd = 64 mod l (64 for l >= 64), fb = LDS byte
+            // offset of its pattern entries
+            uint32_t fo[MF], fd[MF], fl[MF], fb[MF];
+    #pragma unroll
+            for (int f = 0; f < MF; ++f) {
+                fl[f] = 0; fd[f] = 0; fo[f] = 0xffffffffu;
+                fb[f] = pat_byte + kPatSmall * 8;
+                if ((uint32_t)f < nfmax && (uint32_t)f < nf) {
+                    const uint32_t l = rinfo.f[f];
+                    const uint32_t rem = mod_var(qs, l);
+                    fl[f] = l;
+                    fo[f] = rem ? l - rem : 0;
+                    fd[f] = l > (uint32_t)kWave ? (uint32_t)kWave : (uint32_t)kWave % l;
+                    if (l < (uint32_t)kWave) fb[f] = pat_byte + c_pat_off[l] * 8;
+                }
+            }
+
+            // ---- windows ----
+            for (uint32_t k = 0; k < nw; ++k) {
+                const uint32_t qb = qs + k * kWave;
+                uint64_t nc = lds64(smem, wheel_lane + o30 * 8);
+    #pragma unroll
+                for (int f = 0; f < MF; ++f) {
+                    if ((uint32_t)f < nfmax) {
+                        const uint32_t idx = fo[f] < (uint32_t)kWave ? fo[f] : (uint32_t)kWave;
+                        nc |= lds64(smem, fb[f] + idx * 8);
+                        // next window: the distance drops by 64 mod l, or
+                        // wraps past a multiple (fo + l - fd < l, no overflow
+                        // for any l < 2^32)
+                        const uint32_t t = fo[f] - fd[f];
+                        fo[f] = fo[f] < fd[f] ? t + fl[f] : t;
                     }
                 }
-            }
-            o30 += kWave % kWheel;
-            if (o30 >= (uint32_t)kWheel) o30 -= kWheel;
-
-            const uint64_t bal = __ballot(alive != 0);
-            if (bal) {
-                const uint32_t pos = qn + lane_rank(bal);
-                if (alive) {
-                    QEntry e;
-                    e.p = p; e.qb = qb; e.mask = alive;
-                    queue[pos] = e;
+                uint64_t alive = ~nc;
+                if (qb < lo_max || qb > edge_hi) {
+                    const uint32_t below = rlo > qb ? rlo - qb : 0;
+                    const uint32_t upto = rhi >= qb ? rhi - qb + 1 : 0;
+                    alive &= (upto < (uint32_t)kWave ? (1ull << upto) - 1 : ~0ull) &
+                             (below < (uint32_t)kWave ? ~0ull << below : 0ull);
                 }
-                qn = uni(qn + (uint32_t)__popcll(bal));
-                if (qn >= (uint32_t)kWave) drain(kWave, R);
+                npairs = __builtin_popcount((uint32_t)alive) + npairs;
+                npairs_hi = __builtin_popcount((uint32_t)(alive >> 32)) + npairs_hi;
+    #pragma unroll
+                for (int d = 0; d < KD; ++d) {
+                    alive &= ~lds64(smem, lb[d] + kk8);
+                    left[d] = __builtin_popcount((uint32_t)alive) + left[d];
+                    left_hi[d] = __builtin_popcount((uint32_t)(alive >> 32)) + left_hi[d];
+                }
+                kk8 += 8;
+                if (kk8 == kDenseExt * 8) {
+                    kk8 = 0;
+    #pragma unroll
+                    for (int d = 0; d < KD; ++d) {
+                        kq[d] += P.dext[d];
+                        if (kq[d] >= P.dr[d]) {
+                            kq[d] -= P.dr[d];
+                            lb[d] += (P.dext[d] - P.dr[d]) * 8;
+                        } else {
+                            lb[d] += P.dext[d] * 8;
+                        }
+                    }
+                }
+                o30 += kWave % kWheel;
+                if (o30 >= (uint32_t)kWheel) o30 -= kWheel;
+
+                const uint64_t bal = __ballot(alive != 0);
+                if (bal) {
+                    const uint32_t pos = qn + lane_rank(bal);
+                    if (alive) {
+                        QEntry e;
+                        e.p = p; e.qb = qb; e.mask = alive;
+                        queue[pos] = e;
+                    }
+                    qn = uni(qn + (uint32_t)__popcll(bal));
+                    if (qn >= (uint32_t)kWave) drain(kWave, R);
+                }
             }
+            u += nw;
+            since_flush = uni(since_flush + nw);
+            if (since_flush >= kFlushWindows) flush(R);
         }
-        u += nw;
-        since_flush = uni(since_flush + nw);
-        if (u >= uend || since_flush >= kFlushWindows) flush(R);
     }
+    if (held) flush(R);
 }
 
 // ---- survivor sort: block bitonic sort of 1024, then rank-based merges ----
@@ -453,6 +508,7 @@ hipError_t launch_sweep(const SweepParams &P, int grid, size_t lds_bytes, uint32
                         hipStream_t s) {
     if (P.K > (uint32_t)kKMax) return hipErrorInvalidValue;
     if (P.n_units == 0 && !P.units_dev) return hipSuccess;
+    if (!P.claim) return hipErrorInvalidValue;
     const dim3 g(grid), b(kWave * kWavesPerWG);
     const int mf = sweep_factor_slots(max_p);
 #define CUBOID_SWEEP_K(k)                                                                      \

@@ -18,7 +18,6 @@ constexpr uint32_t kMaxPrimes = 6542;                 // primes below 2^16
 constexpr uint32_t kResidentRowsMax = 1u << 24;       // rows with resident factor lists
 constexpr uint64_t kBandRows = 1u << 22;              // rows per band beyond that
 constexpr uint64_t kMaxSurvScratch = 1ull << 26;      // survivors held on the device per call
-constexpr uint32_t kDefaultLdsBudget = 32 * 1024;     // LDS bytes for dense window tables
 constexpr uint64_t kMaxOrderRows = 1ull << 27;        // rows regrouped per call
 constexpr uint64_t kBucketMinRows = 128;              // smaller requests keep their row order
 constexpr uint64_t kReplicaBytes = 32ull << 20;       // budget for counter replicas

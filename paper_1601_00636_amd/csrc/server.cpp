@@ -281,7 +281,7 @@ int launch(cuboid_server *S, StreamState &st) {
         SRVCHK(launch_bucket_rows((const ReqDesc *)(dv + o_bdesc), nb, (const uint64_t *)(dv + o_cpre),
                                   chunk_pre.back(), (const uint64_t *)(dv + o_rpre),
                                   (uint32_t *)S->arena_buf.p, st.s));
-    SRVCHK(launch_fill_u64((uint64_t *)st.surv_n.p, 1, 0, st.s));
+    SRVCHK(launch_fill_u64((uint64_t *)st.surv_n.p, 2, 0, st.s));
     SweepParams P;
     memset(&P, 0, sizeof(P));
     const DenseSet &ds = *S->ds;
@@ -310,6 +310,8 @@ int launch(cuboid_server *S, StreamState &st) {
     P.surv = (SurvEntry *)st.surv.p;
     P.surv_cap = kSurvPool;
     P.surv_n = (unsigned long long *)st.surv_n.p;
+    P.claim = (unsigned long long *)st.surv_n.p + 1;
+    P.schedule = S->tun.schedule;
     uint32_t max_p = 0;
     for (const auto &d : descs) max_p = std::max(max_p, d.p1);
     const size_t lds = (size_t)ds.words * 8 + kSweepFixedLds;
@@ -505,7 +507,7 @@ int cuboid_server_start(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_prim
         SRVCHK(hipStreamCreateWithFlags(&sst.s, hipStreamNonBlocking));
         SRVCHK(hipEventCreateWithFlags(&sst.ev, hipEventDisableTiming));
         SRVCHK(sst.surv.ensure(kSurvPool * sizeof(SurvEntry)));
-        SRVCHK(sst.surv_n.ensure(8));
+        SRVCHK(sst.surv_n.ensure(16));   // survivor count, claim counter
     }
     ctx->servers.fetch_add(1);
     cuboid_server *raw = S.release();

@@ -157,6 +157,26 @@ def test_long_rows(ctx, primes):
         _cmp(res, ref)
 
 
+@pytest.mark.parametrize("rect", [
+    (4294967291, 4294967291, 4294900000, 4294967295),   # the largest prime below 2^32
+    (4294967279, 4294967291, 4294960000, 4294967295),
+    (2147483659, 2147483659, 2147400000, 2147500000),   # a prime just above 2^31
+])
+def test_prime_rows_above_2_31(ctx, rect):
+    # rows whose own prime factor exceeds 2^31, over thousands of windows:
+    # the distance to the next multiple of p must wrap without overflowing,
+    # so that exactly the column q = p drops out as not coprime
+    primes = wl.PRIMES_C2
+    ref = oracle.sieve(*rect, primes)
+    for wg in (0, 1):
+        cb.cuboid_set_tuning(ctx, primes, workgroups=wg)
+        try:
+            res = cb.cuboid_sieve_range(ctx, *rect, primes, cap=1 << 16)
+        finally:
+            cb.cuboid_set_tuning(ctx, primes)
+        _cmp(res, ref)
+
+
 @pytest.mark.parametrize("k", [0, 1, 3, 5, 7, 9, 12])
 def test_dense_count_does_not_change_results(ctx, k):
     primes = wl.primes_upto(120, 3)
@@ -307,3 +327,32 @@ def test_c4_sample_against_oracle(ctx):
     assert st == cb.OK
     for ref in g["results"]:
         _cmp(out[ref["index"]], ref)
+
+
+# ---------------------------------------------------------------- work sharing
+
+@pytest.mark.parametrize("schedule", [1, 2])
+@pytest.mark.parametrize("wg", [0, 1, 3])
+def test_both_work_schedules(ctx, schedule, wg):
+    # round-robin pieces and the shared counter (forced at sizes where the
+    # default would pick the other) give the oracle's results: one rectangle,
+    # a batch of many, rows beyond the resident table (one launch per row
+    # window, each with its own counter) and long rows
+    primes = wl.PRIMES_C2
+    cb.cuboid_set_tuning(ctx, primes, workgroups=wg, schedule=schedule)
+    try:
+        for rect in ((1, 3000, 1, 2000), (16777000, 16777300, 5, 900), (1, 70, 1, 300000)):
+            _cmp(cb.cuboid_sieve_range(ctx, *rect, primes, cap=1 << 16), oracle.sieve(*rect, primes))
+        rects = wl.random_rectangles(40, seed=77, max_coord=50000, max_side=700)
+        st, out = cb.cuboid_sieve_batch(ctx, rects, primes, caps=4096)
+        assert st == cb.OK
+        for rect, r in zip(rects, out):
+            _cmp(r, oracle.sieve(*rect, primes))
+    finally:
+        cb.cuboid_set_tuning(ctx, primes)
+
+
+def test_schedule_out_of_range(ctx):
+    with pytest.raises(cb.CuboidError) as e:
+        cb.cuboid_set_tuning(ctx, wl.PRIMES_C2, schedule=3)
+    assert e.value.status == cb.E_ARG

@@ -147,3 +147,20 @@ def test_section6_scan_against_the_oracle(ctx):
     assert got["n_survivors"] == g["n_survivors"] == 0
     assert [int(x) for x in got["r_max"]] == g["r_max"]
     assert g["max_depth_prime"] == 137
+
+
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_region_under_both_work_schedules(ctx, schedule):
+    # the region scan of rows 1..4000 with primes 11..541 under each way of
+    # sharing units between waves, against the default
+    primes = wl.PRIMES_PAPER
+    ref = cb.cuboid_sieve_region(ctx, 1, 4000, primes, band_rows=100)
+    cb.cuboid_set_tuning(ctx, primes, schedule=schedule, workgroups=5)
+    try:
+        got = cb.cuboid_sieve_region(ctx, 1, 4000, primes, band_rows=100)
+    finally:
+        cb.cuboid_set_tuning(ctx, primes)
+    assert got["n_pairs"] == ref["n_pairs"]
+    assert [int(c) for c in got["counts"]] == [int(c) for c in ref["counts"]]
+    assert got["survivors"] == ref["survivors"]
+    assert [int(x) for x in got["r_max"]] == [int(x) for x in ref["r_max"]]
