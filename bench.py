@@ -182,6 +182,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=64)
     ap.add_argument("--served-seconds", type=float, default=10.0)
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON-lines file the autotuner reads its choice from, or appends it to "
+                         "(lets a profiled run skip the tuning sweeps)")
     ap.add_argument("--section6-only", action="store_true",
                     help="only run the region scan of the paper's section 6 (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -210,7 +213,7 @@ def main():
         return 0
     reqs = wl.batched_requests(4096)
     primes = wl.PRIMES_BATCHED
-    tun = cb.cuboid_autotune_for(ctx, primes, reqs)
+    tun = cb.cuboid_autotune_for(ctx, primes, reqs, cache_path=args.tune_cache)
     cb.cuboid_enable_timing(ctx, True)
     _, trivial = cb.cuboid_canonical_primes(primes)
     trivial = np.array([r in (2, 3, 5, 7) for r in primes])

@@ -309,7 +309,7 @@ typedef struct cuboid_tuning {
     uint32_t lds_budget;     /* bytes of LDS allowed for the dense windows
                                 (0 = all that a workgroup has left)         */
     uint32_t schedule;       /* how waves share a launch's units: 0 = by size
-                                (pieces of up to 64 units dealt round-robin below
+                                (pieces of up to 256 units dealt round-robin below
                                 16384 units per wave, else a shared counter),
                                 1 = round-robin pieces, 2 = shared counter   */
 } cuboid_tuning;

@@ -129,7 +129,7 @@ __device__ __forceinline__ uint64_t lds64(const unsigned char *base, uint32_t by
 
 constexpr uint32_t kFlushWindows = 1u << 19;   // per-lane u32 counters stay below 2^31
 constexpr uint64_t kMinClaim = 16;             // smallest piece taken from the shared counter
-constexpr uint64_t kPiece = 64;                // largest round-robin piece
+constexpr uint64_t kPiece = 256;               // largest round-robin piece
 constexpr uint64_t kGuidedUnitsPerWave = 16384;  // the shared counter from this many units per wave
 
 // KD dense primes; MF factor slots (enough for every row of the launch)
@@ -229,8 +229,9 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
     // serialise, so it pays only once waves hold many units each.
     const bool guided =
         P.schedule == 2 || (P.schedule == 0 && n_units >= nwaves * kGuidedUnitsPerWave);
-    // a small launch deals smaller pieces, so that every wave gets some
-    const uint64_t per_wave = n_units / nwaves;
+    // about eight pieces per wave, at most kPiece units each (a small launch
+    // deals small pieces, so that every wave gets some)
+    const uint64_t per_wave = n_units / nwaves / 8;
     const uint64_t psize = per_wave < 1 ? 1 : (per_wave < kPiece ? per_wave : kPiece);
     uint64_t piece = w;
     for (;;) {
