@@ -204,19 +204,20 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
         since_flush = 0;
     };
 
-    // The wave's counters hold counts of request R = req[ri] only: they are
-    // flushed when the wave moves on to another request, every kFlushWindows
-    // windows, and once at the end.
-    ReqDesc R;
-    uint32_t held = 0;   // R loaded (wave-uniform)
+    // The wave's counters hold counts of request req[ri] only: they are
+    // flushed when the wave moves on to another request, before a segment
+    // that would take them past kFlushWindows windows, and once at the end.
+    // The descriptor is re-read where needed rather than kept live across
+    // the loops.
+    uint32_t held = 0;   // counters may hold counts of req[ri] (wave-uniform)
     auto load = [&](uint32_t i) {
-        R = P.req[i];
-        R.p0 = uni(R.p0); R.p1 = uni(R.p1); R.q0 = uni(R.q0); R.q1 = uni(R.q1);
-        R.nrb = uni(R.nrb); R.nwin = uni(R.nwin); R.unit0 = uni64(R.unit0);
-        R.rows_p0 = uni(R.rows_p0); R.ip0 = uni(R.ip0);
-        R.ulo = uni64(R.ulo); R.ucount = uni64(R.ucount); R.slot = uni(R.slot);
-        R.flags = uni(R.flags);
-        held = 1;
+        ReqDesc D = P.req[i];
+        D.p0 = uni(D.p0); D.p1 = uni(D.p1); D.q0 = uni(D.q0); D.q1 = uni(D.q1);
+        D.nrb = uni(D.nrb); D.nwin = uni(D.nwin); D.unit0 = uni64(D.unit0);
+        D.rows_p0 = uni(D.rows_p0); D.ip0 = uni(D.ip0);
+        D.ulo = uni64(D.ulo); D.ucount = uni64(D.ucount); D.slot = uni(D.slot);
+        D.flags = uni(D.flags);
+        return D;
     };
 
     // How the waves share the units.  Round-robin: wave w takes pieces w,
@@ -235,7 +236,8 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
     const uint64_t psize = per_wave < 1 ? 1 : (per_wave < kPiece ? per_wave : kPiece);
     uint64_t piece = w;
     for (;;) {
-        uint64_t u, uend;
+        uint64_t u = 0, uend = 0;
+        bool done;
         if (guided) {
             uint64_t start = 0, take = 0;
             if (lane == 0) {
@@ -246,18 +248,19 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
             }
             u = uni64(start);
             take = uni64(take);
-            if (u >= n_units) break;
-            uend = n_units - u < take ? n_units : u + take;
+            done = u >= n_units;
+            if (!done) uend = n_units - u < take ? n_units : u + take;
         } else {
             u = piece * psize;
-            if (u >= n_units) break;
-            uend = n_units - u < psize ? n_units : u + psize;
+            done = u >= n_units;
+            if (!done) uend = n_units - u < psize ? n_units : u + psize;
             piece += nwaves;
         }
         // request holding unit u: the last i with req[i].unit0 <= u, at or after
         // ri since a wave's pieces only move forward (gallop, then bisect)
-        {
-            uint32_t lo = ri, step = 1;
+        uint32_t lo = ri;
+        if (!done) {
+            uint32_t step = 1;
             while (lo + step < P.n_req && uni64(P.req[lo + step].unit0) <= u) {
                 lo += step;
                 step <<= 1;
@@ -268,16 +271,23 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
                 if (uni64(P.req[mid].unit0) <= u) lo = mid; else hi = mid;
             }
             lo = uni(lo);
-            if (held && lo != ri) flush(R);
-            ri = lo;
-            load(ri);
         }
+        // the counters go out when the wave leaves the request, and at the end
+        if (held && (done || lo != ri)) {
+            flush(load(ri));
+            held = 0;
+        }
+        if (done) break;
+        ri = lo;
         while (u < uend) {
+            const ReqDesc R = load(ri);
             const uint64_t rend = R.unit0 + R.ucount;
-            if (u >= rend) {
-                flush(R);
+            const bool past = u >= rend;
+            if (held && (past || since_flush >= kFlushWindows)) flush(R);
+            held = 1;
+            if (past) {
+                held = 0;
                 ri = uni(ri + 1);
-                load(ri);
                 continue;
             }
             const uint64_t local = u - R.unit0 + R.ulo;
@@ -424,10 +434,8 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
             }
             u += nw;
             since_flush = uni(since_flush + nw);
-            if (since_flush >= kFlushWindows) flush(R);
         }
     }
-    if (held) flush(R);
 }
 
 // ---- survivor sort: block bitonic sort of 1024, then rank-based merges ----
