@@ -373,7 +373,8 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
             }
 
             // ---- windows ----
-            for (uint32_t k = 0; k < nw; ++k) {
+            const uint32_t nwu = uni(nw);   // keeps the loop exit scalar
+            for (uint32_t k = 0; k < nwu; ++k) {
                 const uint32_t qb = qs + k * kWave;
                 uint64_t nc = lds64(smem, wheel_lane + o30 * 8);
     #pragma unroll
