@@ -239,6 +239,40 @@ int cuboid_sieve_batch(cuboid_ctx *ctx, const cuboid_request *req, uint32_t n_re
                        const uint32_t *primes, uint32_t n_primes,
                        cuboid_result *res, void *hip_stream);
 
+/*
+ * cuboid_sieve_batch with the results left in device memory, for callers whose
+ * next step runs on the GPU (and to time the sieve without the PCIe transfer
+ * of its results).  The rectangles are read from host memory (16 bytes each,
+ * staged with the launch).  Device buffers, owned by the caller (from
+ * cuboid_device_alloc, or hipMalloc of the HIP runtime this library links):
+ *   counts_dev     [n_req][n_primes] uint64, the order of the prime list
+ *   pairs_dev      [n_req] uint64, coprime pairs p != q of each rectangle
+ *   survivors_dev  surv_cap entries of 16 bytes {uint64 idx; uint32 req;
+ *                  uint32 0}, sorted by (req, idx); idx as in
+ *                  cuboid_sieve_range for rectangle req
+ * *n_survivors (host) receives the total.  Beyond surv_cap the list holds the
+ * first surv_cap in that order and the call returns E_CAPACITY; counts and
+ * pairs are complete either way.  E_LIMIT if more than 2^26 survive (counts
+ * and pairs complete, the list unspecified).  Returns after the results are
+ * in place.  Errors: E_ARG (NULL arrays, n_req == 0), E_RANGE (an invalid
+ * rectangle, before any work), E_PRIMES, E_DEVICE, E_NOT_LOADED.
+ */
+int cuboid_sieve_batch_dev(cuboid_ctx *ctx, const cuboid_request *req, uint32_t n_req,
+                           const uint32_t *primes, uint32_t n_primes, uint64_t *counts_dev,
+                           uint64_t *pairs_dev, void *survivors_dev, uint64_t surv_cap,
+                           uint64_t *n_survivors, void *hip_stream);
+
+/*
+ * Device memory on the context's GPU for the _dev entry points, and a
+ * synchronous copy back to host memory (on hip_stream, NULL = the context's
+ * stream).  cuboid_device_free waits for the context's stream first; NULL is a
+ * no-op.  Errors: E_ARG (bytes == 0 for alloc, NULL pointers), E_DEVICE.
+ */
+int cuboid_device_alloc(cuboid_ctx *ctx, size_t bytes, void **out);
+int cuboid_device_free(cuboid_ctx *ctx, void *p);
+int cuboid_device_read(cuboid_ctx *ctx, void *dst, const void *src_dev, size_t bytes,
+                       void *hip_stream);
+
 /* ------------------------------------------------------------------ served */
 
 /*

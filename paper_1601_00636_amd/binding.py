@@ -103,6 +103,11 @@ def _load():
         "cuboid_exact_value": ([u32, u32, u64, ctypes.c_char_p, ctypes.c_size_t], i32),
         "cuboid_canonical_primes": ([P(u32), u32, P(u32), P(u8)], i32),
         "cuboid_sieve_batch": ([vp, P(cuboid_request), u32, P(u32), u32, P(cuboid_result), vp], i32),
+        "cuboid_sieve_batch_dev": ([vp, P(cuboid_request), u32, P(u32), u32, vp, vp, vp, u64,
+                                    P(u64), vp], i32),
+        "cuboid_device_alloc": ([vp, ctypes.c_size_t, P(vp)], i32),
+        "cuboid_device_free": ([vp, vp], i32),
+        "cuboid_device_read": ([vp, vp, vp, ctypes.c_size_t, vp], i32),
         "cuboid_autotune": ([vp, P(u32), u32, ctypes.c_char_p, P(cuboid_tuning)], i32),
         "cuboid_autotune_for": ([vp, P(u32), u32, P(cuboid_request), u32, ctypes.c_char_p,
                                  P(cuboid_tuning)], i32),
@@ -372,6 +377,77 @@ class BatchResult:
 
     def __iter__(self):
         return (self[i] for i in range(len(self)))
+
+
+def cuboid_device_alloc(ctx, nbytes):
+    """Device memory on the context's GPU (an int address)."""
+    ptr = ctypes.c_void_p()
+    _check(_load().cuboid_device_alloc(ctx, int(nbytes), ctypes.byref(ptr)), "cuboid_device_alloc")
+    return int(ptr.value)
+
+
+def cuboid_device_free(ctx, ptr):
+    _check(_load().cuboid_device_free(ctx, ctypes.c_void_p(int(ptr)) if ptr else None),
+           "cuboid_device_free")
+
+
+def cuboid_device_read(ctx, ptr, out, stream=None):
+    """Copy len(out) elements' bytes from device address ptr into the numpy array out."""
+    out = np.ascontiguousarray(out)
+    _check(_load().cuboid_device_read(ctx, out.ctypes.data_as(ctypes.c_void_p),
+                                      ctypes.c_void_p(int(ptr)), out.nbytes, _stream(stream)),
+           "cuboid_device_read")
+    return out
+
+
+_SURV_DEV_DTYPE = np.dtype([("idx", "<u8"), ("req", "<u4"), ("pad", "<u4")])
+
+
+class DeviceBatch:
+    """Device buffers for cuboid_sieve_batch_dev: counts [n_req][n_primes],
+    pairs [n_req], surv_cap survivor entries.  read() brings them back."""
+
+    def __init__(self, ctx, n_req, n_primes, surv_cap=0):
+        self.ctx, self.n_req, self.n_primes, self.surv_cap = ctx, int(n_req), int(n_primes), int(surv_cap)
+        self.counts = cuboid_device_alloc(ctx, max(1, self.n_req * self.n_primes) * 8)
+        self.pairs = cuboid_device_alloc(ctx, max(1, self.n_req) * 8)
+        self.surv = cuboid_device_alloc(ctx, self.surv_cap * 16) if self.surv_cap else 0
+        self.n_survivors = 0
+
+    def read(self):
+        counts = cuboid_device_read(self.ctx, self.counts,
+                                    np.empty((self.n_req, self.n_primes), dtype=np.uint64))
+        pairs = cuboid_device_read(self.ctx, self.pairs, np.empty(self.n_req, dtype=np.uint64))
+        k = min(self.n_survivors, self.surv_cap)
+        surv = (cuboid_device_read(self.ctx, self.surv, np.empty(k, dtype=_SURV_DEV_DTYPE))
+                if k else np.empty(0, dtype=_SURV_DEV_DTYPE))
+        return counts, pairs, surv
+
+    def free(self):
+        for a in ("counts", "pairs", "surv"):
+            if getattr(self, a):
+                cuboid_device_free(self.ctx, getattr(self, a))
+                setattr(self, a, 0)
+
+
+def cuboid_sieve_batch_dev(ctx, requests, primes, dev, stream=None):
+    """requests: (n, 4) array-like of (p0, p1, q0, q1); dev: a DeviceBatch of
+    the same n and prime count.  Returns the status; dev.n_survivors is set."""
+    pr = _arr(primes, np.uint32)
+    reqa = np.ascontiguousarray(np.asarray(requests, dtype=np.uint32).reshape(-1, 4))
+    n = reqa.shape[0]
+    if n != dev.n_req or len(pr) != dev.n_primes:
+        raise ValueError("device buffers are for %d requests x %d primes" % (dev.n_req, dev.n_primes))
+    ns = ctypes.c_uint64(0)
+    st = _load().cuboid_sieve_batch_dev(ctx, reqa.ctypes.data_as(P(cuboid_request)), n, _p(pr, u32),
+                                        len(pr), ctypes.c_void_p(dev.counts),
+                                        ctypes.c_void_p(dev.pairs),
+                                        ctypes.c_void_p(dev.surv) if dev.surv else None,
+                                        dev.surv_cap, ctypes.byref(ns), _stream(stream))
+    dev.n_survivors = int(ns.value)
+    if st not in (OK, E_CAPACITY, E_LIMIT):
+        _check(st, "cuboid_sieve_batch_dev")
+    return st
 
 
 def cuboid_sieve_batch(ctx, requests, primes, caps=1024, stream=None, out=None):

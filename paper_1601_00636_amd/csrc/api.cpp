@@ -294,6 +294,77 @@ int cuboid_sieve_batch(cuboid_ctx *ctx, const cuboid_request *req, uint32_t n_re
     return any_cap ? CUBOID_E_CAPACITY : CUBOID_OK;
 }
 
+int cuboid_sieve_batch_dev(cuboid_ctx *ctx, const cuboid_request *req, uint32_t n_req,
+                           const uint32_t *primes, uint32_t n_primes, uint64_t *counts_dev,
+                           uint64_t *pairs_dev, void *survivors_dev, uint64_t surv_cap,
+                           uint64_t *n_survivors, void *hip_stream) {
+    if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
+    if (!req || n_req == 0 || n_req == 0xffffffffu || !counts_dev || !pairs_dev || !n_survivors ||
+        (surv_cap && !survivors_dev))
+        return CUBOID_E_ARG;
+    *n_survivors = 0;
+    for (uint32_t i = 0; i < n_req; ++i)
+        if (rect_valid(req[i].p0, req[i].p1, req[i].q0, req[i].q1)) return CUBOID_E_RANGE;
+    std::vector<uint32_t> sorted;
+    int st = canonical_primes(primes, n_primes, &sorted);
+    if (st) return st;
+    CtxLock g(ctx);
+    if (set_device(ctx)) return CUBOID_E_DEVICE;
+    const std::vector<uint32_t> caller(primes, primes + n_primes);
+    SieveOut &so = ctx->h_out;
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    DevOut dev;
+    dev.counts = counts_dev;
+    dev.pairs = pairs_dev;
+    dev.surv = (SurvEntry *)survivors_dev;
+    dev.surv_cap = surv_cap;
+    // the survivor scratch holds the caller's capacity; when more survive
+    // (within the device scratch) the call runs again with room for all, so
+    // that the first surv_cap in (request, index) order are the right ones
+    st = sieve_rects(ctx, caller, req, n_req, std::max<uint64_t>(surv_cap, 1), s, &so, &dev);
+    if (st && st != CUBOID_E_LIMIT) return st;
+    if (so.n_surv > std::max<uint64_t>(surv_cap, 1) && so.n_surv <= kMaxSurvScratch) {
+        st = sieve_rects(ctx, caller, req, n_req, so.n_surv, s, &so, &dev);
+        if (st && st != CUBOID_E_LIMIT) return st;
+    }
+    *n_survivors = so.n_surv;
+    if (st == CUBOID_E_LIMIT || so.n_surv > kMaxSurvScratch) return CUBOID_E_LIMIT;
+    return so.n_surv > surv_cap ? CUBOID_E_CAPACITY : CUBOID_OK;
+}
+
+int cuboid_device_alloc(cuboid_ctx *ctx, size_t bytes, void **out) {
+    if (!out) return CUBOID_E_ARG;
+    *out = nullptr;
+    if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
+    if (bytes == 0) return CUBOID_E_ARG;
+    CtxLock g(ctx);
+    if (set_device(ctx)) return CUBOID_E_DEVICE;
+    return hipMalloc(out, bytes) == hipSuccess ? CUBOID_OK : CUBOID_E_DEVICE;
+}
+
+int cuboid_device_free(cuboid_ctx *ctx, void *p) {
+    if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
+    if (!p) return CUBOID_OK;
+    CtxLock g(ctx);
+    if (set_device(ctx)) return CUBOID_E_DEVICE;
+    // work of this context that may still read the buffer ends first
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return CUBOID_E_DEVICE;
+    return hipFree(p) == hipSuccess ? CUBOID_OK : CUBOID_E_DEVICE;
+}
+
+int cuboid_device_read(cuboid_ctx *ctx, void *dst, const void *src_dev, size_t bytes,
+                       void *hip_stream) {
+    if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
+    if (bytes && (!dst || !src_dev)) return CUBOID_E_ARG;
+    if (!bytes) return CUBOID_OK;
+    CtxLock g(ctx);
+    if (set_device(ctx)) return CUBOID_E_DEVICE;
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    if (hipMemcpyAsync(dst, src_dev, bytes, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return CUBOID_E_DEVICE;
+    return hipStreamSynchronize(s) == hipSuccess ? CUBOID_OK : CUBOID_E_DEVICE;
+}
+
 int cuboid_canonical_primes(const uint32_t *primes, uint32_t n, uint32_t *sorted_out,
                             uint8_t *trivial_out) {
     if (!sorted_out) return CUBOID_E_ARG;

@@ -452,6 +452,18 @@ int fetch_survivors(cuboid_ctx *ctx, uint64_t n, std::vector<SurvEntry> *out, hi
     return CUBOID_OK;
 }
 
+// Sorted survivors into the caller's device buffer (the first dev.surv_cap).
+int place_survivors(cuboid_ctx *ctx, uint64_t n, const DevOut &dev, hipStream_t s) {
+    SurvEntry *sorted = nullptr;
+    HIPCHK(launch_sort_surv((SurvEntry *)ctx->surv.p, (SurvEntry *)ctx->surv_tmp.p,
+                            (const unsigned long long *)ctx->surv_n.p, n, &sorted, s));
+    const uint64_t k = std::min<uint64_t>(n, dev.surv_cap);
+    static_assert(sizeof(SurvEntry) == 16, "survivor entry is two words");
+    if (k) HIPCHK(launch_copy_u64((uint64_t *)dev.surv, (const uint64_t *)sorted, 2 * k, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return CUBOID_OK;
+}
+
 // For each prime of the caller's list, its index among the plan's
 // non-trivial primes (canonical counter slot), or -1 for a trivial prime.
 std::vector<int32_t> count_columns(const Plan &pl, const std::vector<uint32_t> &caller) {
@@ -478,8 +490,9 @@ int rect_valid(uint32_t p0, uint32_t p1, uint32_t q0, uint32_t q1) {
 // descriptor split at window edges.
 int sieve_core(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid_tuning &tun,
                std::vector<ReqDesc> &reqs, uint32_t n_slots, const std::vector<int32_t> *col,
-               uint64_t surv_cap, hipStream_t s, CoreOut *out) {
+               uint64_t surv_cap, hipStream_t s, CoreOut *out, const DevOut *dev) {
     const uint32_t nc = ds.K + ds.n_deep;
+    if (dev && !col) return CUBOID_E_ARG;   // device results are in the caller's prime order
     // counters come back per slot either canonical (nc) or already in the
     // caller's prime order (col: the counter of each caller prime, -1 for a
     // trivial one), gathered on the device
@@ -514,7 +527,7 @@ int sieve_core(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid
     }
     if (resident && ctx->use_graphs) {
         // clears, sweep, replica sums and downloads all inside the graph
-        st = run_batch_graph(ctx, pl, ds, tun, reqs, n_slots, col, surv_cap, s, &out->units);
+        st = run_batch_graph(ctx, pl, ds, tun, reqs, n_slots, col, surv_cap, s, &out->units, dev);
         if (st) return st;
         HIPCHK(hipStreamSynchronize(s));
         st = sweep_time();
@@ -569,19 +582,25 @@ int sieve_core(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid
         const void *csrc = ctx->counts.p;
         if (col && ncount) {
             HIPCHK(ctx->colbuf.ensure(width * 4));
-            HIPCHK(ctx->gathered.ensure(ncount * 8));
+            if (!dev) HIPCHK(ctx->gathered.ensure(ncount * 8));
+            // the destination is taken after the ensure: growing reallocates
+            void *gdst = dev ? (void *)dev->counts : ctx->gathered.p;
             HIPCHK(hipMemcpyAsync(ctx->colbuf.p, col->data(), width * 4, hipMemcpyHostToDevice, s));
             HIPCHK(launch_gather_counts((const unsigned long long *)ctx->counts.p,
                                         (const int32_t *)ctx->colbuf.p, n_slots, nc, width,
-                                        (unsigned long long *)ctx->gathered.p, s));
-            csrc = ctx->gathered.p;
+                                        (unsigned long long *)gdst, s));
+            csrc = gdst;
         }
-        // results through pinned staging: counts, pairs, survivor count
+        // results through pinned staging (counts, pairs, survivor count), or
+        // into the caller's device buffers with only the survivor count staged
         HIPCHK(ctx->result_stage.ensure((ncount + n_slots + 1) * 8));
         uint64_t *rs = (uint64_t *)ctx->result_stage.p;
-        if (ncount)
+        if (ncount && !dev)
             HIPCHK(hipMemcpyAsync(rs, csrc, ncount * 8, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(rs + ncount, ctx->pairs.p, (size_t)n_slots * 8, hipMemcpyDeviceToHost, s));
+        if (dev)
+            HIPCHK(launch_copy_u64(dev->pairs, (const uint64_t *)ctx->pairs.p, n_slots, s));
+        else
+            HIPCHK(hipMemcpyAsync(rs + ncount, ctx->pairs.p, (size_t)n_slots * 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(rs + ncount + n_slots, ctx->surv_n.p, 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
     }
@@ -589,12 +608,13 @@ int sieve_core(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid
     out->nc = nc;
     out->n_slots = n_slots;
     out->width = width;
-    out->counts = stage;
-    out->pairs = stage + ncount;
+    out->counts = dev ? nullptr : stage;
+    out->pairs = dev ? nullptr : stage + ncount;
     out->n_surv = stage[ncount + n_slots];
     out->surv.clear();
     if (out->n_surv > 0 && out->n_surv <= surv_cap) {
-        st = fetch_survivors(ctx, out->n_surv, &out->surv, s);
+        st = dev ? place_survivors(ctx, out->n_surv, *dev, s)
+                 : fetch_survivors(ctx, out->n_surv, &out->surv, s);
         if (st) return st;
     }
     return CUBOID_OK;
@@ -630,7 +650,7 @@ void record_timing(cuboid_ctx *ctx, hipStream_t s, const CoreOut &co, const Dens
 // The plain and batched sieve share this path.  `rects` are validated.
 int sieve_rects(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes,
                 const cuboid_request *rects, uint32_t n_req, uint64_t surv_cap_total,
-                hipStream_t s, SieveOut *out) {
+                hipStream_t s, SieveOut *out, const DevOut *dev) {
     Plan *pl = nullptr;
     DenseSet *ds = nullptr;
     cuboid_tuning tun;
@@ -649,7 +669,7 @@ int sieve_rects(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes,
     if (ctx->timing) HIPCHK(hipEventRecord(ctx->ev_total0, s));
     const std::vector<int32_t> col = count_columns(*pl, caller_primes);
     CoreOut &co = ctx->h_core;
-    st = sieve_core(ctx, *pl, *ds, tun, reqs, n_req, &col, surv_cap, s, &co);
+    st = sieve_core(ctx, *pl, *ds, tun, reqs, n_req, &col, surv_cap, s, &co, dev);
     if (st) return st;
     out->n_req = n_req;
     out->n_primes = (uint32_t)caller_primes.size();

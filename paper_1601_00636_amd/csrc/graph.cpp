@@ -75,6 +75,8 @@ struct GraphArgs {
     Layout L;
     uint32_t n, n_slots, nc, np, grid;
     bool gather;                  // counts come back in the caller's prime order
+    uint64_t *dcounts;            // device destinations (cuboid_sieve_batch_dev), else null:
+    uint64_t *dpairs;             //   results go to the pinned result staging
     size_t lds;
     uint32_t max_p;
     bool timing;
@@ -109,15 +111,18 @@ hipError_t build_graph(cuboid_ctx *ctx, const GraphArgs &a, hipStream_t s, Batch
                                            ctx->rep_stride_pairs, s);
             const void *csrc = ctx->counts.p;
             if (r == hipSuccess && a.gather && nout) {
+                void *gdst = a.dcounts ? (void *)a.dcounts : ctx->gathered.p;
                 r = launch_gather_counts((const unsigned long long *)ctx->counts.p,
                                          (const int32_t *)(a.block + a.L.o_col), ns, nc, a.np,
-                                         (unsigned long long *)ctx->gathered.p, s);
-                csrc = ctx->gathered.p;
+                                         (unsigned long long *)gdst, s);
+                csrc = gdst;
             }
             // no counters when every prime is trivial; capture refuses empty copies
-            if (r == hipSuccess && nout)
+            if (r == hipSuccess && nout && !a.dcounts)
                 r = hipMemcpyAsync(a.result, csrc, nout * 8, hipMemcpyDeviceToHost, s);
-            if (r == hipSuccess)
+            if (r == hipSuccess && a.dpairs)
+                r = launch_copy_u64(a.dpairs, (const uint64_t *)ctx->pairs.p, ns, s);
+            else if (r == hipSuccess)
                 r = hipMemcpyAsync(a.result + nout, ctx->pairs.p, (size_t)ns * 8,
                                    hipMemcpyDeviceToHost, s);
             if (r == hipSuccess)
@@ -174,11 +179,13 @@ void drop_graphs(cuboid_ctx *ctx) {
 // Resident-row batch as one graph launch on `s`; the caller synchronizes `s`
 // before reading counts, pair counts and the survivor count from the result
 // staging ([n_slots * width] counts | [n_slots] pairs | survivor count), width
-// being nc, or the caller's prime count when `col` maps them.
+// being nc, or the caller's prime count when `col` maps them.  With `dev`
+// (and `col`), counts and pair counts go to the caller's device buffers and
+// only the survivor count to the staging.
 int run_batch_graph(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid_tuning &tun,
                     std::vector<ReqDesc> &reqs, uint32_t n_slots,
                     const std::vector<int32_t> *col, uint64_t surv_cap, hipStream_t s,
-                    uint64_t *units_out) {
+                    uint64_t *units_out, const DevOut *dev) {
     const uint32_t n = (uint32_t)reqs.size();
     const uint32_t nc = ds.K + ds.n_deep;
     LaunchShape &sh = ctx->h_shape;
@@ -223,6 +230,8 @@ int run_batch_graph(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const c
     a.nc = nc;
     a.np = np;
     a.gather = col != nullptr;
+    a.dcounts = dev ? dev->counts : nullptr;
+    a.dpairs = dev ? dev->pairs : nullptr;
     a.grid = tun.workgroups;
     a.lds = lds;
     a.max_p = sh.max_p;
@@ -244,6 +253,8 @@ int run_batch_graph(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const c
     put(&key, np);
     put(&key, (uint32_t)a.gather);
     put(&key, (const void *)ctx->gathered.p);
+    put(&key, (const void *)a.dcounts);
+    put(&key, (const void *)a.dpairs);
     put(&key, a.grid);
     put(&key, (uint32_t)sweep_factor_slots(sh.max_p));
     put(&key, (uint32_t)a.timing);

@@ -23,6 +23,14 @@ __global__ void fill_u64_kernel(uint64_t *p, uint64_t n, uint64_t v) {
         p[i] = v;
 }
 
+// Device-to-device copy as a kernel (also valid inside a captured graph and
+// for buffers of any HIP allocator of this process).
+__global__ void copy_u64_kernel(uint64_t *dst, const uint64_t *src, uint64_t n) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 __global__ void fill_u8_kernel(uint8_t *p, uint64_t n, uint8_t v) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
@@ -374,8 +382,16 @@ __global__ void reduce_replicas_kernel(unsigned long long *buf, uint64_t n, uint
 
 }  // namespace
 
+hipError_t launch_copy_u64(uint64_t *dst, const uint64_t *src, uint64_t n, hipStream_t s) {
+    if (!n) return hipSuccess;
+    if (!dst || !src) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(copy_u64_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s) {
     if (!n) return hipSuccess;
+    if (!p) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, p, n, v);
     return hipGetLastError();
 }
@@ -504,6 +520,7 @@ hipError_t launch_gather_counts(const unsigned long long *counts, const int32_t 
                                 unsigned long long *out, hipStream_t s) {
     const uint64_t n = (uint64_t)n_slots * np;
     if (!n) return hipSuccess;
+    if (!counts || !col || !out) return hipErrorInvalidValue;
     hipLaunchKernelGGL(gather_counts_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, counts, col,
                        n_slots, nc, np, out);
     return hipGetLastError();

@@ -98,6 +98,16 @@ struct CoreOut {
     uint64_t units = 0;
     double sweep_ms = 0;
 };
+// Device destinations of a call's results (cuboid_sieve_batch_dev): counts
+// (in the caller's prime order) and pair counts written by kernels into the
+// caller's device buffers, the sorted survivor list copied there too; only
+// the survivor count comes back to the host.
+struct DevOut {
+    uint64_t *counts = nullptr;   // [n_slots][caller primes]
+    uint64_t *pairs = nullptr;    // [n_slots]
+    SurvEntry *surv = nullptr;    // first surv_cap entries, sorted by (slot, idx)
+    uint64_t surv_cap = 0;
+};
 // Results of one sieve call over several rectangles.
 struct SieveOut {
     uint32_t n_req = 0, n_primes = 0;
@@ -196,7 +206,7 @@ int rect_valid(uint32_t p0, uint32_t p1, uint32_t q0, uint32_t q1);
 void shape_reqs(cuboid_ctx *ctx, std::vector<ReqDesc> &reqs, LaunchShape *sh);
 int sieve_core(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid_tuning &tun,
                std::vector<ReqDesc> &reqs, uint32_t n_slots, const std::vector<int32_t> *col,
-               uint64_t surv_cap, hipStream_t s, CoreOut *out);
+               uint64_t surv_cap, hipStream_t s, CoreOut *out, const DevOut *dev = nullptr);
 int prepare_primes(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes, Plan **pl,
                    cuboid_tuning *tun, DenseSet **ds);
 void record_timing(cuboid_ctx *ctx, hipStream_t s, const CoreOut &co, const DenseSet &ds,
@@ -210,10 +220,10 @@ SweepParams sweep_params(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, co
 int run_batch_graph(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid_tuning &tun,
                     std::vector<ReqDesc> &reqs, uint32_t n_slots,
                     const std::vector<int32_t> *col, uint64_t surv_cap, hipStream_t s,
-                    uint64_t *units_out);
+                    uint64_t *units_out, const DevOut *dev = nullptr);
 void drop_graphs(cuboid_ctx *ctx);
 int sieve_rects(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes,
                 const cuboid_request *rects, uint32_t n_req, uint64_t surv_cap_total,
-                hipStream_t s, SieveOut *out);
+                hipStream_t s, SieveOut *out, const DevOut *dev = nullptr);
 
 }  // namespace cuboid

@@ -101,6 +101,20 @@ def test_calls_on_null_context_are_refused():
     with pytest.raises(cb.CuboidError) as e:
         cb.cuboid_write_table_files(h, [11], "/nonexistent/t.bin", "/nonexistent/p.bin")
     assert e.value.status == cb.E_NOT_LOADED
+    with pytest.raises(cb.CuboidError) as e:
+        cb.cuboid_device_alloc(h, 64)
+    assert e.value.status == cb.E_NOT_LOADED
+    with pytest.raises(cb.CuboidError) as e:
+        cb.cuboid_autotune_for(bogus, [11], [(1, 2, 1, 2)])
+    assert e.value.status == cb.E_NOT_LOADED
+    lib = cb.lib()
+    n = ctypes.c_uint64(7)
+    req = (ctypes.c_uint32 * 4)(1, 5, 1, 5)
+    pr = (ctypes.c_uint32 * 1)(11)
+    assert lib.cuboid_sieve_batch_dev(h, ctypes.cast(req, ctypes.POINTER(cb.cuboid_request)), 1,
+                                      pr, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), None, 0,
+                                      ctypes.byref(n), None) == cb.E_NOT_LOADED
+    assert lib.cuboid_device_read(h, None, None, 0, None) == cb.E_NOT_LOADED
 
 
 def test_bench_refuses_more_than_one_gpu():

@@ -317,13 +317,22 @@ def test_batch_capacity_per_request(ctx):
     _cmp(out[0], oracle.sieve(1, 200, 1, 200, wl.PRIMES_C1))
 
 
-def test_c4_sample_against_oracle(ctx):
+@pytest.mark.parametrize("tuned", [False, True])
+def test_c4_sample_against_oracle(ctx, tuned):
+    # the full 4096-rectangle batch, with the default tuning and with the one
+    # the benchmark runs (tuned on the same rectangles), sampled requests
+    # against the oracle's
     if not os.path.exists(golden_path("oracle_c4s.json")):
         pytest.skip("c4 sample golden missing")
     g = _golden("oracle_c4s.json")
     reqs = wl.batched_requests(4096)
-    _say("c4: 4096 rectangles in one batch")
-    st, out = cb.cuboid_sieve_batch(ctx, reqs, g["primes"], caps=64)
+    _say("c4: 4096 rectangles in one batch, tuned=%s" % tuned)
+    if tuned:
+        cb.cuboid_autotune_for(ctx, g["primes"], reqs)
+    try:
+        st, out = cb.cuboid_sieve_batch(ctx, reqs, g["primes"], caps=64)
+    finally:
+        cb.cuboid_set_tuning(ctx, g["primes"])
     assert st == cb.OK
     for ref in g["results"]:
         _cmp(out[ref["index"]], ref)
