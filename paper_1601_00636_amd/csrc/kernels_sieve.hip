@@ -335,8 +335,12 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
             if (p == 1 && rlo < 2) rlo = 2;   // (1, 1) is coprime but p = q
             const uint32_t lo_max = uni(wave_max(rlo));
             const uint32_t hi_min = uni(wave_min(rhi));
-            // a window starting above edge_hi reaches past hi_min
+            // a window starting above edge_hi reaches past hi_min; windows
+            // k < k_lo start below lo_max and windows k >= k_hi reach past
+            // hi_min: only those take the per-lane masks
             const uint32_t edge_hi = hi_min >= (uint32_t)(kWave - 1) ? hi_min - (kWave - 1) : 0;
+            const uint32_t k_lo = uni(lo_max > qs ? (lo_max - qs - 1) / kWave + 1 : 0);
+            const uint32_t k_hi = uni(edge_hi >= qs ? (edge_hi - qs) / kWave + 1 : 0);
 
             // dense prime d: the window starting at column qs (offset o = qs mod
             // r) is entry k0 = o / 64 mod r of the lane's row, the following ones
@@ -390,7 +394,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
                     }
                 }
                 uint64_t alive = ~nc;
-                if (qb < lo_max || qb > edge_hi) {
+                if (k < k_lo || k >= k_hi) {
                     const uint32_t below = rlo > qb ? rlo - qb : 0;
                     const uint32_t upto = rhi >= qb ? rhi - qb + 1 : 0;
                     alive &= (upto < (uint32_t)kWave ? (1ull << upto) - 1 : ~0ull) &
