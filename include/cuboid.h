@@ -227,7 +227,7 @@ typedef struct cuboid_result {
 /*
  * Many rectangles in one persistent launch: every request's outputs are those
  * cuboid_sieve_range would give for it alone (bit-exact).  Work is split into
- * 64-row x 64-column units and spread evenly over the whole GPU regardless of
+ * 64-row x 64-column units shared out over the whole GPU regardless of
  * request sizes.  Returns E_CAPACITY if any request's status is E_CAPACITY
  * (the others are complete); an invalid rectangle sets that request's status
  * to E_RANGE and fails the call with E_RANGE before any work.  Returns E_LIMIT

@@ -1,11 +1,12 @@
 // The sieve sweep of arXiv:1601.00636, section 2, on CDNA4.
 //
-// Each wavefront owns 64 consecutive rows p (one per lane) and walks the
-// columns q in windows of 64, so one 64-bit mask per lane holds the state of
-// 64 pairs.  Per window:
+// Each wavefront owns 64 rows p (one per lane; the rows of a request, taken in
+// an order that groups them by number of prime factors) and walks the columns
+// q in windows of 64, so one 64-bit mask per lane holds the state of 64 pairs.
+// Per window:
 //   1. coprimality (Conjecture 1.1 domain): a wheel lookup clears the q sharing
-//      a factor 2, 3, 5 or 7 with p, and each larger prime factor of p clears
-//      its multiples by a shifted bit pattern;
+//      a factor 2, 3 or 5 with p, and each prime factor >= 7 of p clears its
+//      multiples by a shifted bit pattern;
 //   2. dense primes: for the first K non-trivial primes r (ascending) one LDS
 //      read fetches u_r(p mod r, q mod r) for all 64 columns at once, the
 //      pairs it rejects are counted for r and dropped;
@@ -14,8 +15,9 @@
 //      primes in ascending order through the ratio-form tables, so the first
 //      rejecting prime is counted and unrejected pairs are appended as
 //      survivors.
-// The flattened space of 64x64 units over all requests of a launch is split
-// evenly over the persistent grid.
+// The flattened space of 64x64 units over all requests of a launch is shared
+// by the waves of a persistent grid, in round-robin pieces or through a
+// shared counter (see the work-sharing comment in the kernel).
 #include "devmath.h"
 #include "internal.h"
 
