@@ -368,6 +368,10 @@ def main():
 
     if not args.no_extras:
         res["extras"]["section6_scan"] = section6_scan(cb, wl, ctx, stream, torch)
+        # measured throughputs of the two units that bound the sweep
+        pk = cb.cuboid_probe_peaks(ctx)
+        res["extras"]["measured_peaks"] = dict(pk, sweep_lane_ops_frac_of_measured=(
+            res["roofline"]["achieved"] * 1e12 / pk["valu_lane_ops_per_s"]))
 
     if not args.no_extras and args.served_seconds > 0:
         res["extras"]["served"] = run_served(cb, wl, ctx, primes, args.served_seconds)

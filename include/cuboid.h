@@ -269,6 +269,14 @@ int cuboid_sieve_batch_dev(cuboid_ctx *ctx, const cuboid_request *req, uint32_t 
  * no-op.  Errors: E_ARG (bytes == 0 for alloc, NULL pointers), E_DEVICE.
  */
 int cuboid_device_alloc(cuboid_ctx *ctx, size_t bytes, void **out);
+/*
+ * Measured peaks of the context's GPU for the sweep's roofline: lane-
+ * operations per second of v_bcnt_u32_b32 over 8 independent chains per lane
+ * at full occupancy, and bytes per second of conflict-free 64-bit LDS reads
+ * (8 workgroups of 256 lanes per compute unit, a few milliseconds each).
+ * Errors: E_ARG (NULL outputs), E_DEVICE.
+ */
+int cuboid_probe_peaks(cuboid_ctx *ctx, double *valu_lane_ops_per_s, double *lds_bytes_per_s);
 int cuboid_device_free(cuboid_ctx *ctx, void *p);
 int cuboid_device_read(cuboid_ctx *ctx, void *dst, const void *src_dev, size_t bytes,
                        void *hip_stream);

@@ -106,6 +106,7 @@ def _load():
         "cuboid_sieve_batch_dev": ([vp, P(cuboid_request), u32, P(u32), u32, vp, vp, vp, u64,
                                     P(u64), vp], i32),
         "cuboid_device_alloc": ([vp, ctypes.c_size_t, P(vp)], i32),
+        "cuboid_probe_peaks": ([vp, P(ctypes.c_double), P(ctypes.c_double)], i32),
         "cuboid_device_free": ([vp, vp], i32),
         "cuboid_device_read": ([vp, vp, vp, ctypes.c_size_t, vp], i32),
         "cuboid_autotune": ([vp, P(u32), u32, ctypes.c_char_p, P(cuboid_tuning)], i32),
@@ -384,6 +385,13 @@ def cuboid_device_alloc(ctx, nbytes):
     ptr = ctypes.c_void_p()
     _check(_load().cuboid_device_alloc(ctx, int(nbytes), ctypes.byref(ptr)), "cuboid_device_alloc")
     return int(ptr.value)
+
+
+def cuboid_probe_peaks(ctx):
+    """Measured (v_bcnt lane-ops/s, conflict-free LDS read bytes/s) of the context's GPU."""
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _check(_load().cuboid_probe_peaks(ctx, ctypes.byref(a), ctypes.byref(b)), "cuboid_probe_peaks")
+    return {"valu_lane_ops_per_s": a.value, "lds_bytes_per_s": b.value}
 
 
 def cuboid_device_free(ctx, ptr):

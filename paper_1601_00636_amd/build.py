@@ -18,6 +18,7 @@ SOURCES = [
     "kernels_tables.hip",
     "kernels_sieve.hip",
     "kernels_roots.hip",
+    "kernels_peaks.hip",
     "bigint.cpp",
     "graph.cpp",
     "region.cpp",

@@ -365,6 +365,17 @@ int cuboid_device_read(cuboid_ctx *ctx, void *dst, const void *src_dev, size_t b
     return hipStreamSynchronize(s) == hipSuccess ? CUBOID_OK : CUBOID_E_DEVICE;
 }
 
+int cuboid_probe_peaks(cuboid_ctx *ctx, double *valu_lane_ops_per_s, double *lds_bytes_per_s) {
+    if (!valu_lane_ops_per_s || !lds_bytes_per_s) return CUBOID_E_ARG;
+    if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
+    CtxLock g(ctx);
+    if (set_device(ctx)) return CUBOID_E_DEVICE;
+    return run_peak_probes(ctx->cu_count, ctx->stream, valu_lane_ops_per_s, lds_bytes_per_s) ==
+                   hipSuccess
+               ? CUBOID_OK
+               : CUBOID_E_DEVICE;
+}
+
 int cuboid_canonical_primes(const uint32_t *primes, uint32_t n, uint32_t *sorted_out,
                             uint8_t *trivial_out) {
     if (!sorted_out) return CUBOID_E_ARG;

@@ -115,6 +115,9 @@ constexpr size_t kSweepFixedLds = kWheelBytes + kPatBytes + kWavesPerWG * kPerWa
 // ---- kernel launchers (kernels_*.hip) ----
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_copy_u64(uint64_t *dst, const uint64_t *src, uint64_t n, hipStream_t s);
+// measured v_bcnt_u32_b32 lane-operations and conflict-free LDS bytes per second
+hipError_t run_peak_probes(int cu_count, hipStream_t s, double *valu_lane_ops_per_s,
+                           double *lds_bytes_per_s);
 hipError_t launch_fill_u8(uint8_t *p, uint64_t n, uint8_t v, hipStream_t s);
 hipError_t launch_q_eval(const uint32_t *p, const uint32_t *q, const uint32_t *t,
                          const uint32_t *r, uint64_t n, uint32_t *out, hipStream_t s);

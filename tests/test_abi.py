@@ -115,6 +115,8 @@ def test_calls_on_null_context_are_refused():
                                       pr, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), None, 0,
                                       ctypes.byref(n), None) == cb.E_NOT_LOADED
     assert lib.cuboid_device_read(h, None, None, 0, None) == cb.E_NOT_LOADED
+    a, b = ctypes.c_double(), ctypes.c_double()
+    assert lib.cuboid_probe_peaks(h, ctypes.byref(a), ctypes.byref(b)) == cb.E_NOT_LOADED
 
 
 def test_bench_refuses_more_than_one_gpu():
