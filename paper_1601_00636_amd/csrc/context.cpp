@@ -311,8 +311,9 @@ void shape_reqs(cuboid_ctx *ctx, std::vector<ReqDesc> &reqs, LaunchShape *sh) {
         r.ucount = (uint64_t)r.nrb * r.nwin;
         units += r.ucount;
         max_p = std::max(max_p, r.p1);
-        const bool group = ctx->bucketing && rows >= kBucketMinRows &&
-                           sh->row_prefix[i] + rows <= kMaxOrderRows;
+        // band-split region requests keep their rows in natural order
+        const bool group = ctx->bucketing && !(r.flags & kReqBandSplit) &&
+                           rows >= kBucketMinRows && sh->row_prefix[i] + rows <= kMaxOrderRows;
         sh->row_prefix[i + 1] = sh->row_prefix[i] + (group ? rows : 0);
         sh->chunk_prefix[i + 1] =
             sh->chunk_prefix[i] + (group ? (rows + kBucketChunk - 1) / kBucketChunk : 0);
@@ -396,6 +397,7 @@ int launch_reqs(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboi
     SweepParams P =
         sweep_params(ctx, pl, ds, (const ReqDesc *)ctx->reqbuf.p, n, sh.units, surv_cap);
     P.schedule = tun.schedule;
+    for (const ReqDesc &d : reqs) P.band_split |= (d.flags & kReqBandSplit) ? 1u : 0u;
     const size_t lds = (size_t)ds.words * 8 + kSweepFixedLds;
     if (lds > ctx->max_lds) return CUBOID_E_LIMIT;
     // a call may launch once per row window: each launch hands out its units

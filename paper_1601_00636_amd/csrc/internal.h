@@ -58,12 +58,18 @@ struct ReqDesc {
     uint32_t ip0;          // p0 of the caller's rectangle (survivor indices)
     const uint32_t *order; // rows in processing order, or null for p0, p0 + 1, ...
     const uint8_t *nfac;   // number of f[] of p at nfac[p - rows_p0]
+    uint32_t band_rows;    // kReqBandSplit: row p counts into slot
+    uint32_t band_p0;      //   slot + (p - band_p0) / band_rows
 };
 
 // The columns of row p are min(cbrt(p / 9), p / 59) <= q <= 59 p (Theorem 1.2)
 // intersected with [q0, q1], and survivors are tagged p * 2^32 + q.  Needs
 // p <= 72796055 so that 59 p < 2^32.
 constexpr uint32_t kReqRegion = 1;
+// A region request over several report bands of band_rows >= 64 rows, rows in
+// natural order: a 64-row block then spans at most two bands, and each lane's
+// counts go to the slot of its own row's band.
+constexpr uint32_t kReqBandSplit = 2;
 constexpr uint32_t kRegionMaxP = 72796055u;
 
 struct SurvEntry {
@@ -95,7 +101,7 @@ struct SweepParams {
     unsigned long long *counts;          // [n_rep][slot][nc], canonical ascending order
     unsigned long long *pairs;           // [n_rep][slot]
     uint32_t n_rep;                      // counter replicas (power of two), by wave
-    uint32_t pad1;
+    uint32_t band_split;                 // some request is kReqBandSplit
     uint64_t rep_stride_counts;          // elements between replicas
     uint64_t rep_stride_pairs;
     SurvEntry *surv;

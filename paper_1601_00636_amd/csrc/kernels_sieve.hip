@@ -86,10 +86,16 @@ __constant__ uint16_t c_pat_off[64] = {
     0, 371, 0, 430, 0, 0};
 
 // Tests the pairs of one queued window against the deep primes, in ascending
-// order; counts the first rejecting prime, appends unrejected pairs.
+// order; counts the first rejecting prime, appends unrejected pairs.  Counts
+// of the wave's current slot `slot0` go to its LDS counters, counts of another
+// slot (the second band of a band-split row block) straight to global memory.
+template <bool SPLIT>
 __device__ __forceinline__ void deep_window(const SweepParams &P, const QEntry e,
-                                            const ReqDesc &R, uint32_t *dcnt,
+                                            const ReqDesc &R, uint32_t slot0, uint32_t *dcnt,
                                             unsigned long long *cnt_rep) {
+    const uint32_t slot = (SPLIT && (R.flags & kReqBandSplit))
+                              ? R.slot + (e.p - R.band_p0) / R.band_rows
+                              : R.slot;
     uint64_t mask = e.mask;
     const uint64_t width = (uint64_t)R.q1 - R.q0 + 1;
     while (mask) {
@@ -103,10 +109,10 @@ __device__ __forceinline__ void deep_window(const SweepParams &P, const QEntry e
             if (a == 0 || b == 0) continue;
             const uint32_t x = mulr(a, P.ipool[d.ioff + b], d.r, d.m);
             if (P.vpool[d.voff + x]) {
-                if (i < kDeepCounters)
+                if (i < kDeepCounters && (!SPLIT || slot == slot0))
                     atomicAdd(&dcnt[i], 1u);
                 else
-                    atomicAdd(&cnt_rep[(uint64_t)R.slot * P.nc + P.K + i], 1ull);
+                    atomicAdd(&cnt_rep[(uint64_t)slot * P.nc + P.K + i], 1ull);
                 rejected = true;
                 break;
             }
@@ -117,7 +123,7 @@ __device__ __forceinline__ void deep_window(const SweepParams &P, const QEntry e
                 SurvEntry s;
                 s.idx = (R.flags & kReqRegion) ? ((uint64_t)e.p << 32) | q
                                                : (uint64_t)(e.p - R.ip0) * width + (q - R.q0);
-                s.req = R.slot;
+                s.req = slot;
                 s.pad = 0;
                 P.surv[pos] = s;
             }
@@ -134,8 +140,9 @@ constexpr uint64_t kMinClaim = 16;             // smallest piece taken from the 
 constexpr uint64_t kPiece = 256;               // largest round-robin piece
 constexpr uint64_t kGuidedUnitsPerWave = 16384;  // the shared counter from this many units per wave
 
-// KD dense primes; MF factor slots (enough for every row of the launch)
-template <int KD, int MF>
+// KD dense primes; MF factor slots (enough for every row of the launch);
+// SPLIT: the launch holds band-split region requests
+template <int KD, int MF, bool SPLIT>
 __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepParams P) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid >> 6;
@@ -168,29 +175,44 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
     uint32_t npairs = 0, npairs_hi = 0;
     uint32_t qn = 0;            // queued windows (wave-uniform)
     uint32_t since_flush = 0;   // windows since counters were flushed (wave-uniform)
+    // counter slot of the held counts (wave-uniform); lanes with cup set hold
+    // counts of slot cslot + 1 (the second band of a band-split row block)
+    uint32_t cslot = 0;
+    bool cup = false;
 
     auto drain = [&](uint32_t n, const ReqDesc &R) {
         __builtin_amdgcn_wave_barrier();
-        if (lane < n) deep_window(P, queue[qn - n + lane], R, dcnt, cnt_rep);
+        if (lane < n) deep_window<SPLIT>(P, queue[qn - n + lane], R, cslot, dcnt, cnt_rep);
         __builtin_amdgcn_wave_barrier();
         qn = uni(qn - n);
     };
 
     auto flush = [&](const ReqDesc &R) {
         while (qn) drain(qn < (uint32_t)kWave ? qn : (uint32_t)kWave, R);
-        const uint64_t cbase = (uint64_t)R.slot * P.nc;
+        const uint64_t cbase = (uint64_t)cslot * P.nc;
+        const bool two = SPLIT && __ballot(cup) != 0;
         uint32_t before = npairs + npairs_hi;
 #pragma unroll
         for (int k = 0; k < KD; ++k) {
             const uint32_t now = left[k] + left_hi[k];
-            const uint32_t s = wave_sum(before - now);
+            const uint32_t v = before - now;
+            const uint32_t s = wave_sum(cup ? 0u : v);
             if (lane == 0 && s) atomicAdd(&cnt_rep[cbase + k], (unsigned long long)s);
+            if (two) {
+                const uint32_t s1 = wave_sum(cup ? v : 0u);
+                if (lane == 0 && s1) atomicAdd(&cnt_rep[cbase + P.nc + k], (unsigned long long)s1);
+            }
             before = now;
             left[k] = 0;
             left_hi[k] = 0;
         }
-        const uint32_t s = wave_sum(npairs + npairs_hi);
-        if (lane == 0 && s) atomicAdd(&pairs_rep[R.slot], (unsigned long long)s);
+        const uint32_t np = npairs + npairs_hi;
+        const uint32_t s = wave_sum(cup ? 0u : np);
+        if (lane == 0 && s) atomicAdd(&pairs_rep[cslot], (unsigned long long)s);
+        if (two) {
+            const uint32_t s1 = wave_sum(cup ? np : 0u);
+            if (lane == 0 && s1) atomicAdd(&pairs_rep[cslot + 1], (unsigned long long)s1);
+        }
         npairs = 0;
         npairs_hi = 0;
         __builtin_amdgcn_wave_barrier();
@@ -208,7 +230,8 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
 
     // The wave's counters hold counts of request req[ri] only: they are
     // flushed when the wave moves on to another request, before a segment
-    // that would take them past kFlushWindows windows, and once at the end.
+    // that would take them past kFlushWindows windows (before every segment
+    // of a band-split request), and once at the end.
     // The descriptor is re-read where needed rather than kept live across
     // the loops.
     uint32_t held = 0;   // counters may hold counts of req[ri] (wave-uniform)
@@ -285,7 +308,9 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
             const ReqDesc R = load(ri);
             const uint64_t rend = R.unit0 + R.ucount;
             const bool past = u >= rend;
-            if (held && (past || since_flush >= kFlushWindows)) flush(R);
+            // in a band-split request the next segment's lanes hold other rows
+            if (held && (past || since_flush >= kFlushWindows || (SPLIT && (R.flags & kReqBandSplit))))
+                flush(R);
             held = 1;
             if (past) {
                 held = 0;
@@ -319,6 +344,17 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
                     rinfo = R.rows[p - R.rows_p0];
                     rinfo.meta &= ~8u;
                 }
+            }
+            // counter slot: the request's, or in a band-split request the band
+            // of each lane's row (two bands at most in a block of 64 rows)
+            if (SPLIT && (R.flags & kReqBandSplit)) {
+                const uint32_t band = p ? (p - R.band_p0) / R.band_rows : 0xffffffffu;
+                const uint32_t b0 = uni(wave_min(band));
+                cslot = uni(R.slot + b0);
+                cup = p && band != b0;
+            } else {
+                cslot = R.slot;
+                cup = false;
             }
             const uint32_t nf = (rinfo.meta >> 4) & 15;
             const uint32_t nfmax = uni(wave_max(nf));
@@ -527,11 +563,13 @@ hipError_t launch_sweep(const SweepParams &P, int grid, size_t lds_bytes, uint32
     if (!P.claim) return hipErrorInvalidValue;
     const dim3 g(grid), b(kWave * kWavesPerWG);
     const int mf = sweep_factor_slots(max_p);
+#define CUBOID_SWEEP_KS(k, sp)                                                                 \
+    if (mf == 4) hipLaunchKernelGGL((sweep_kernel<k, 4, sp>), g, b, lds_bytes, s, P);           \
+    else if (mf == 5) hipLaunchKernelGGL((sweep_kernel<k, 5, sp>), g, b, lds_bytes, s, P);      \
+    else hipLaunchKernelGGL((sweep_kernel<k, 7, sp>), g, b, lds_bytes, s, P);
 #define CUBOID_SWEEP_K(k)                                                                      \
     case k:                                                                                    \
-        if (mf == 4) hipLaunchKernelGGL((sweep_kernel<k, 4>), g, b, lds_bytes, s, P);           \
-        else if (mf == 5) hipLaunchKernelGGL((sweep_kernel<k, 5>), g, b, lds_bytes, s, P);      \
-        else hipLaunchKernelGGL((sweep_kernel<k, 7>), g, b, lds_bytes, s, P);                   \
+        if (P.band_split) { CUBOID_SWEEP_KS(k, true) } else { CUBOID_SWEEP_KS(k, false) }       \
         break;
     switch (P.K) {
         CUBOID_SWEEP_K(0) CUBOID_SWEEP_K(1) CUBOID_SWEEP_K(2) CUBOID_SWEEP_K(3)
@@ -541,6 +579,7 @@ hipError_t launch_sweep(const SweepParams &P, int grid, size_t lds_bytes, uint32
         default: return hipErrorInvalidValue;
     }
 #undef CUBOID_SWEEP_K
+#undef CUBOID_SWEEP_KS
     return hipGetLastError();
 }
 

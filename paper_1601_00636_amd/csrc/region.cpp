@@ -5,10 +5,13 @@
 // Rows are grouped into report bands of `band_rows` consecutive p (the
 // paper's progress report uses hundreds), one counter slot per band, so the
 // deepest prime used in each band comes out of its first-rejecter counts.
-// Inside a band, rows go to the sweep as sub-requests whose column range is
+// Rows go to the sweep as sub-requests whose column range is
 // [qmin(first row), 59 * last row]; each lane then keeps only its own row's
 // columns.  Sub-requests hold about p / 64 rows, so the spread of 59 p over a
-// sub-request stays near 1/64 of a row's length.
+// sub-request stays near 1/64 of a row's length.  With bands of 64 rows or
+// more, sub-requests run across band edges and every lane counts into its own
+// row's band, so no lane idles at a band's last, partial block of 64 rows;
+// narrower bands get sub-requests of their own.
 #include <string.h>
 
 #include <algorithm>
@@ -69,7 +72,30 @@ int region_sieve(cuboid_ctx *ctx, uint32_t p0, uint32_t p1, uint32_t band_rows,
         const uint32_t nb = (uint32_t)std::min<uint64_t>(kSlotsPerCall, n_bands - b0);
         std::vector<ReqDesc> &reqs = ctx->h_reqs;
         reqs.clear();
-        for (uint32_t j = 0; j < nb; ++j) {
+        if (band_rows >= (uint32_t)kWave) {
+            // sub-requests run across band edges; each lane counts into the
+            // slot of its own row's band (a 64-row block meets two at most)
+            const uint64_t first = p0 + b0 * band_rows;
+            const uint64_t last = std::min<uint64_t>(p1, first + (uint64_t)nb * band_rows - 1);
+            for (uint64_t a = first; a <= last;) {
+                const uint64_t e = std::min<uint64_t>(last, a + sub_rows(a) - 1);
+                const uint32_t j = (uint32_t)((a - first) / band_rows);
+                ReqDesc d;
+                memset(&d, 0, sizeof(d));
+                d.p0 = (uint32_t)a;
+                d.p1 = (uint32_t)e;
+                d.q0 = region_qmin_host((uint32_t)a);
+                d.q1 = 59u * (uint32_t)e;
+                d.ip0 = (uint32_t)a;
+                d.slot = j;
+                d.flags = kReqRegion | kReqBandSplit;
+                d.band_rows = band_rows;
+                d.band_p0 = (uint32_t)(first + (uint64_t)j * band_rows);
+                reqs.push_back(d);
+                a = e + 1;
+            }
+        }
+        for (uint32_t j = 0; j < nb && band_rows < (uint32_t)kWave; ++j) {
             const uint64_t ba = p0 + (b0 + j) * band_rows;
             const uint64_t bb = std::min<uint64_t>(p1, ba + band_rows - 1);
             for (uint64_t a = ba; a <= bb;) {
