@@ -75,6 +75,16 @@ def test_region_survivors_small_primes(ctx):
     assert max(int(x) for x in got["r_max"]) == 31
 
 
+@pytest.mark.parametrize("band", [64, 65, 100, 256])
+def test_region_bands_split_across_row_blocks(ctx, band):
+    # bands of 64 rows or more share row blocks (each lane counts into its own
+    # row's band): survivors, totals and every band's r_max against the oracle
+    primes = [31, 13, 3, 11, 7, 17, 19, 29, 23, 5]
+    got, _ = _check_slice(ctx, 3, 700, primes, band)
+    assert got["n_survivors"] > 10
+    assert got["survivors"] == sorted(got["survivors"])
+
+
 def test_region_matches_rectangles_rowwise_beyond_resident_rows(ctx):
     # rows above 2^24 use row windows computed on the fly; each row of the
     # region equals the rectangle [p, p] x [qmin(p), 59 p]
