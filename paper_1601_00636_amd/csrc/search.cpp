@@ -24,7 +24,7 @@ using namespace cuboid;
 namespace {
 
 constexpr uint32_t kSearchMinP = 152;           // (5.2) holds from p = 152 on
-constexpr uint64_t kChunkPairs = 250000000000ull;   // about 50 ms of sweep
+constexpr uint64_t kChunkPairs = 250000000000ull;   // some 15-50 ms of sweep
 constexpr uint64_t kChunkMaxRows = 1u << 20;
 constexpr uint64_t kKeepSurvivors = 1u << 20;
 constexpr uint64_t kChunkSurvCap = 1u << 16;
