@@ -242,6 +242,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
         D.rows_p0 = uni(D.rows_p0); D.ip0 = uni(D.ip0);
         D.ulo = uni64(D.ulo); D.ucount = uni64(D.ucount); D.slot = uni(D.slot);
         D.flags = uni(D.flags);
+        D.band_rows = uni(D.band_rows); D.band_p0 = uni(D.band_p0);
         return D;
     };
 
