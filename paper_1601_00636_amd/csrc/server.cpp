@@ -12,6 +12,7 @@
 // admits pending requests as slots and arena space free up, and refills idle
 // streams, so requests arriving while others run join the next launch.
 #include <string.h>
+#include <sys/prctl.h>
 
 #include <algorithm>
 #include <chrono>
@@ -399,6 +400,9 @@ int complete(cuboid_server *S, StreamState &st) {
 
 void worker_main(cuboid_server *S) {
     (void)hipSetDevice(S->ctx->device);
+    // while launches are in flight the loop below checks their events every
+    // 2 us; the default 50 us timer slack would stretch each of those sleeps
+    (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
     std::unique_lock<std::mutex> lk(S->mu);
     for (;;) {
         bool progress = false;
@@ -444,7 +448,7 @@ void worker_main(cuboid_server *S) {
         for (auto &st : S->streams) busy = busy || st->busy || !st->queue.empty();
         if (S->stopping && !busy) break;
         if (!progress) {
-            if (busy) S->cv_work.wait_for(lk, std::chrono::microseconds(20));
+            if (busy) S->cv_work.wait_for(lk, std::chrono::microseconds(2));
             else S->cv_work.wait_for(lk, std::chrono::milliseconds(5));
         }
     }
