@@ -180,7 +180,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--cpu-stride", type=int, default=64)
+    ap.add_argument("--cpu-stride", type=int, default=32)
     ap.add_argument("--served-seconds", type=float, default=10.0)
     ap.add_argument("--tune-cache", default=None,
                     help="JSON-lines file the autotuner reads its choice from, or appends it to "
