@@ -103,8 +103,11 @@ def run_cpu_baseline(reqs, primes, stride):
     except OSError:
         pass
     return dict(value=pairs / dt, unit="coprime pairs/s", cores=threads, kind="oracle",
-                sample="every %dth of the 4096 batched rectangles (%d rectangles, %d coprime "
-                       "pairs) in %.1f s; tables excluded" % (stride, len(sample), pairs, dt),
+                sample="every %d%s of the 4096 batched rectangles (%d rectangles, %d coprime "
+                       "pairs) in %.1f s; tables excluded"
+                       % (stride, {1: "st", 2: "nd", 3: "rd"}.get(stride % 10 if stride % 100 not in
+                                                                (11, 12, 13) else 0, "th"),
+                          len(sample), pairs, dt),
                 single_core={"value": pairs1 / dt1, "sample": "the first 8 of those rectangles "
                              "(%d coprime pairs) in %.1f s" % (pairs1, dt1)},
                 cpu_model=model, host_threads=os.cpu_count())
