@@ -371,6 +371,28 @@ def main():
 
     if not args.no_extras:
         res["extras"]["section6_scan"] = section6_scan(cb, wl, ctx, stream, torch)
+        # the background search of section 5 from Start_searching(152, 3), for
+        # about two seconds: pairs sieved per second and how far it got
+        h = cb.cuboid_search_start(ctx, wl.PRIMES_PAPER, 152, 3)
+        t0 = time.perf_counter()
+        time.sleep(2.0)
+        rep = cb.cuboid_search_stop(h)
+        dt = time.perf_counter() - t0
+        res["extras"]["search"] = {"from": [152, 3], "seconds": dt, "exit_p": rep["p"],
+                                   "exit_q": rep["q"], "r_max": rep["r_max"],
+                                   "coprime_pairs": rep["pairs"], "survivors": rep["survivors"],
+                                   "value": rep["pairs"] / dt}
+        # a deep prime list: the 1193 primes 11..9697 (the paper's format
+        # limit) on a 32768 x 32768 square from 10^6
+        deep = wl.primes_upto(9697, 11)
+        sq = (10**6, 10**6 + 32767, 10**6, 10**6 + 32767)
+        rd = cb.cuboid_sieve_range(ctx, *sq, deep, stream=stream)
+        t0 = time.perf_counter()
+        rd = cb.cuboid_sieve_range(ctx, *sq, deep, stream=stream)
+        dt = time.perf_counter() - t0
+        res["extras"]["deep_list_9697"] = {"primes": len(deep), "n_pairs": rd["n_pairs"],
+                                           "survivors": rd["n_survivors"], "ms": dt * 1e3,
+                                           "value": rd["n_pairs"] / dt}
         # measured throughputs of the two units that bound the sweep
         pk = cb.cuboid_probe_peaks(ctx)
         res["extras"]["measured_peaks"] = dict(pk, sweep_lane_ops_frac_of_measured=(
