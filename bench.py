@@ -382,6 +382,18 @@ def main():
                                    "exit_q": rep["q"], "r_max": rep["r_max"],
                                    "coprime_pairs": rep["pairs"], "survivors": rep["survivors"],
                                    "value": rep["pairs"] / dt}
+        # the paper's table files for its 96 primes, written and read back
+        import tempfile
+        with tempfile.TemporaryDirectory() as td:
+            tp, pp_ = os.path.join(td, "tables.bin"), os.path.join(td, "primes.bin")
+            t0 = time.perf_counter()
+            cb.cuboid_write_table_files(ctx, wl.PRIMES_PAPER, tp, pp_)
+            t1 = time.perf_counter()
+            back = cb.cuboid_check_table_files(ctx, tp, pp_)
+            t2 = time.perf_counter()
+            res["extras"]["table_files_11_541"] = {
+                "primes": len(back), "tables_bytes": os.path.getsize(tp),
+                "write_ms": (t1 - t0) * 1e3, "check_ms": (t2 - t1) * 1e3}
         # a deep prime list: the 1193 primes 11..9697 (the paper's format
         # limit) on a 32768 x 32768 square from 10^6
         deep = wl.primes_upto(9697, 11)
