@@ -329,13 +329,23 @@ def test_c4_sample_against_oracle(ctx, tuned):
     _say("c4: 4096 rectangles in one batch, tuned=%s" % tuned)
     if tuned:
         cb.cuboid_autotune_for(ctx, g["primes"], reqs)
+    dev = cb.DeviceBatch(ctx, len(reqs), len(g["primes"]), surv_cap=1 << 16)
     try:
         st, out = cb.cuboid_sieve_batch(ctx, reqs, g["primes"], caps=64)
+        # the benchmark's own step: results left in device memory
+        st_dev = cb.cuboid_sieve_batch_dev(ctx, reqs, g["primes"], dev)
+        counts, pairs, surv = dev.read()
     finally:
+        dev.free()
         cb.cuboid_set_tuning(ctx, g["primes"])
-    assert st == cb.OK
+    assert st == cb.OK and st_dev == cb.OK
     for ref in g["results"]:
-        _cmp(out[ref["index"]], ref)
+        i = ref["index"]
+        _cmp(out[i], ref)
+        assert int(pairs[i]) == ref["n_pairs"]
+        assert [int(c) for c in counts[i]] == [int(c) for c in ref["counts"]]
+        assert [int(e["idx"]) for e in surv if int(e["req"]) == i] == [int(x) for x in ref["survivors"]]
+    assert np.array_equal(counts, out.counts.astype(np.uint64))
 
 
 # ---------------------------------------------------------------- work sharing
