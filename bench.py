@@ -368,6 +368,19 @@ def main():
                                       "ms": float(np.median(reps)) * 1e3,
                                       "sweep_ms": t3["sweep_ms"], "n_pairs": r3["n_pairs"],
                                       "sweep_pairs_per_s": r3["n_pairs"] / (t3["sweep_ms"] * 1e-3)}
+        # the two small plain configurations: [1, 200]^2 with 3..31 and
+        # [1, 10^4]^2 with 3..97, median of 5 calls each (latency-bound)
+        for name, (side, prs) in (("plain_square_200", (200, wl.PRIMES_C1)),
+                                  ("plain_square_1e4", (10**4, wl.PRIMES_C2))):
+            r = cb.cuboid_sieve_range(ctx, 1, side, 1, side, prs, stream=stream)
+            reps = []
+            for _ in range(5):
+                t0 = time.perf_counter()
+                r = cb.cuboid_sieve_range(ctx, 1, side, 1, side, prs, stream=stream)
+                reps.append(time.perf_counter() - t0)
+            dt = float(np.median(reps))
+            extras[name] = {"n_pairs": r["n_pairs"], "survivors": r["n_survivors"],
+                            "ms": dt * 1e3, "value": r["n_pairs"] / dt}
 
     if not args.no_extras:
         res["extras"]["section6_scan"] = section6_scan(cb, wl, ctx, stream, torch)
