@@ -350,10 +350,12 @@ typedef struct cuboid_tuning {
     uint32_t workgroups;     /* persistent grid size (0 = one per compute unit) */
     uint32_t lds_budget;     /* bytes of LDS allowed for the dense windows
                                 (0 = all that a workgroup has left)         */
-    uint32_t schedule;       /* how waves share a launch's units: 0 = by size
-                                (pieces of up to 256 units dealt round-robin below
-                                16384 units per wave, else a shared counter),
-                                1 = round-robin pieces, 2 = shared counter   */
+    uint32_t schedule;       /* how waves share a launch's units: 0 or 3 =
+                                workgroup pieces (pieces dealt round-robin to
+                                the workgroups, taken by their waves through an
+                                LDS cursor), 1 = round-robin pieces per wave,
+                                2 = one shared counter in device memory;
+                                results never depend on it                    */
 } cuboid_tuning;
 
 /*

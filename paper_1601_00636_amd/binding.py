@@ -507,8 +507,8 @@ def cuboid_enable_graphs(ctx, on=True):
 
 
 def cuboid_set_tuning(ctx, primes, dense_primes=None, workgroups=0, lds_budget=0, schedule=0):
-    """No keyword arguments: back to the defaults.  schedule: 0 by size,
-    1 round-robin pieces, 2 shared counter."""
+    """No keyword arguments: back to the defaults.  schedule: 0 or 3 workgroup
+    pieces, 1 round-robin pieces per wave, 2 shared counter."""
     pr = _arr(primes, np.uint32)
     if dense_primes is None and not workgroups and not lds_budget and not schedule:
         _check(_load().cuboid_set_tuning(ctx, _p(pr, u32), len(pr), None), "cuboid_set_tuning")

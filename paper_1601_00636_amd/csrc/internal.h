@@ -96,7 +96,7 @@ struct SweepParams {
     const uint16_t *ipool;               // inverse tables
     const ReqDesc *req;
     uint32_t n_req;
-    uint32_t schedule;                   // 0 by size, 1 round-robin pieces, 2 shared counter
+    uint32_t schedule;                   // 0 or 3 workgroup pieces, 1 round-robin pieces, 2 shared counter
     uint64_t n_units;
     unsigned long long *counts;          // [n_rep][slot][nc], canonical ascending order
     unsigned long long *pairs;           // [n_rep][slot]
@@ -116,7 +116,9 @@ constexpr size_t kWheelBytes = (size_t)kWheelSubsets * kWheel * 8;
 constexpr size_t kQueueEntryBytes = 16;
 constexpr size_t kPerWaveBytes = kQueueCap * kQueueEntryBytes + kDeepCounters * 4;
 constexpr size_t kPatBytes = (size_t)kPatEntries * 8;
-constexpr size_t kSweepFixedLds = kWheelBytes + kPatBytes + kWavesPerWG * kPerWaveBytes;
+constexpr size_t kWgCtlBytes = 16;   // the workgroup's claim cursor
+constexpr size_t kSweepFixedLds =
+    kWheelBytes + kPatBytes + kWavesPerWG * kPerWaveBytes + kWgCtlBytes;
 
 // ---- kernel launchers (kernels_*.hip) ----
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);

@@ -16,8 +16,10 @@
 //      rejecting prime is counted and unrejected pairs are appended as
 //      survivors.
 // The flattened space of 64x64 units over all requests of a launch is shared
-// by the waves of a persistent grid, in round-robin pieces or through a
-// shared counter (see the work-sharing comment in the kernel).
+// by the waves of a persistent grid: pieces dealt round-robin to the
+// workgroups and taken by their waves through an LDS cursor (the default), or
+// round-robin pieces per wave, or a shared counter in global memory (see the
+// work-sharing comment in the kernel).
 #include "devmath.h"
 #include "internal.h"
 
@@ -136,9 +138,10 @@ __device__ __forceinline__ uint64_t lds64(const unsigned char *base, uint32_t by
 }
 
 constexpr uint32_t kFlushWindows = 1u << 19;   // per-lane u32 counters stay below 2^31
-constexpr uint64_t kMinClaim = 16;             // smallest piece taken from the shared counter
+constexpr uint64_t kMinClaim = 16;             // smallest claim from a cursor or counter
 constexpr uint64_t kPiece = 256;               // largest round-robin piece
-constexpr uint64_t kGuidedUnitsPerWave = 16384;  // the shared counter from this many units per wave
+constexpr uint64_t kBigPiece = 4096;           // workgroup pieces of launches with many units
+constexpr uint64_t kWgPieces = 32;             // workgroup pieces per workgroup, at least
 
 // KD dense primes; MF factor slots (enough for every row of the launch);
 // SPLIT: the launch holds band-split region requests
@@ -153,11 +156,14 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
     unsigned char *wave_area = (unsigned char *)(spat + kPatEntries) + (size_t)wv * kPerWaveBytes;
     QEntry *queue = (QEntry *)wave_area;
     uint32_t *dcnt = (uint32_t *)(wave_area + kQueueCap * sizeof(QEntry));
+    unsigned long long *wg_cursor =
+        (unsigned long long *)((unsigned char *)(spat + kPatEntries) + kWavesPerWG * kPerWaveBytes);
 
     for (uint32_t i = tid; i < P.dense_words; i += blockDim.x) sdense[i] = P.dense_tab[i];
     for (uint32_t i = tid; i < kWheelSubsets * kWheel; i += blockDim.x) swheel[i] = P.wheel[i];
     for (uint32_t i = tid; i < (uint32_t)kPatEntries; i += blockDim.x) spat[i] = P.patterns[i];
     for (uint32_t i = lane; i < kDeepCounters; i += kWave) dcnt[i] = 0;
+    if (tid == 0) *wg_cursor = 0;
     __syncthreads();
 
     const uint32_t wheel_byte = P.dense_words * 8;
@@ -246,25 +252,70 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
         return D;
     };
 
-    // How the waves share the units.  Round-robin: wave w takes pieces w,
-    // w + nwaves, w + 2 nwaves, ... of up to kPiece units, so every wave samples
-    // the whole launch (rows come grouped by cost) and no shared state is
-    // touched.  Shared counter: pieces of half the remaining units' even
-    // share per wave, never fewer than kMinClaim (guided self-scheduling);
-    // a wave that drew cheap units comes back for more, so all waves finish
-    // within about one small piece of each other.  The counter's atomics
-    // serialise, so it pays only once waves hold many units each.
-    const bool guided =
-        P.schedule == 2 || (P.schedule == 0 && n_units >= nwaves * kGuidedUnitsPerWave);
+    // How the waves share the units.
+    // Workgroup pieces (schedule 0 or 3): pieces of wg_ps units are dealt
+    // round-robin to the workgroups, so each workgroup samples the whole launch
+    // (rows come grouped by cost); the waves of a workgroup take its units in
+    // order through an LDS cursor, in claims of up to a piece that shrink to
+    // kMinClaim towards the end of the workgroup's share.  Waves sharing a SIMD
+    // progress at unequal rates, so a fixed share per wave leaves the fast ones
+    // idle while the slow ones finish; the cursor keeps them all busy to the end
+    // and costs one LDS atomic per claim.
+    // Round-robin pieces (1): wave w takes pieces w, w + nwaves, ... of up to
+    // kPiece units, touching no shared state.
+    // Shared counter (2): guided self-scheduling on one global counter, each
+    // claim half the remaining units' even share per wave, at least kMinClaim.
+    // Its atomics serialise across the device.
+    const bool wgshare = P.schedule == 0 || P.schedule == 3;
+    const bool guided = P.schedule == 2;
     // about eight pieces per wave, at most kPiece units each (a small launch
     // deals small pieces, so that every wave gets some)
     const uint64_t per_wave = n_units / nwaves / 8;
     const uint64_t psize = per_wave < 1 ? 1 : (per_wave < kPiece ? per_wave : kPiece);
     uint64_t piece = w;
+    uint64_t lcur = 0, lend = 0;   // the wave's claimed units of its workgroup's share
+    // workgroup pieces: at least kWgPieces per workgroup, of up to kPiece units,
+    // or of kBigPiece units in launches that fill them (segments of long rows
+    // then pay their setup and counter flush less often)
+    const uint64_t G = gridDim.x;
+    uint64_t wg_ps = n_units / (G * kWgPieces);
+    wg_ps = wg_ps >= kBigPiece ? kBigPiece : (wg_ps < 1 ? 1 : (wg_ps < kPiece ? wg_ps : kPiece));
     for (;;) {
         uint64_t u = 0, uend = 0;
-        bool done;
-        if (guided) {
+        bool done = false;
+        if (wgshare) {
+            if (lcur >= lend) {
+                const uint64_t n_pieces = (n_units + wg_ps - 1) / wg_ps;
+                const uint64_t share =
+                    n_pieces > blockIdx.x ? (n_pieces - blockIdx.x + G - 1) / G * wg_ps : 0;
+                const uint64_t min_take = wg_ps < kMinClaim ? wg_ps : kMinClaim;
+                uint64_t start = 0, take = 0;
+                if (lane == 0) {
+                    const uint64_t seen = __hip_atomic_load(wg_cursor, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_WORKGROUP);
+                    take = (seen < share ? share - seen : 0) / (2 * kWavesPerWG);
+                    take = take < min_take ? min_take : (take < wg_ps ? take : wg_ps);
+                    start = atomicAdd(wg_cursor, (unsigned long long)take);
+                }
+                lcur = uni64(start);
+                lend = lcur + uni64(take);
+                if (lend > share) lend = share;
+            }
+            if (lcur < lend) {
+                // local unit lcur is unit off of the workgroup's j-th piece; a
+                // claim may run into the next piece, taken on the next pass
+                const uint64_t j = lcur / wg_ps, off = lcur - j * wg_ps;
+                const uint64_t n = lend - lcur < wg_ps - off ? lend - lcur : wg_ps - off;
+                u = (j * G + blockIdx.x) * wg_ps + off;
+                lcur += n;
+                // only the launch's last piece can be partial, and it is the
+                // last piece of its workgroup
+                if (u >= n_units) done = true;
+                else uend = n_units - u < n ? n_units : u + n;
+            } else {
+                done = true;
+            }
+        } else if (guided) {
             uint64_t start = 0, take = 0;
             if (lane == 0) {
                 const uint64_t seen = __hip_atomic_load(P.claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

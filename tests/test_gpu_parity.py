@@ -350,13 +350,13 @@ def test_c4_sample_against_oracle(ctx, tuned):
 
 # ---------------------------------------------------------------- work sharing
 
-@pytest.mark.parametrize("schedule", [1, 2])
+@pytest.mark.parametrize("schedule", [1, 2, 3])
 @pytest.mark.parametrize("wg", [0, 1, 3])
-def test_both_work_schedules(ctx, schedule, wg):
-    # round-robin pieces and the shared counter (forced at sizes where the
-    # default would pick the other) give the oracle's results: one rectangle,
-    # a batch of many, rows beyond the resident table (one launch per row
-    # window, each with its own counter) and long rows
+def test_work_schedules(ctx, schedule, wg):
+    # round-robin pieces per wave, the shared counter and workgroup pieces
+    # (on grids of one, three and all workgroups) give the oracle's results:
+    # one rectangle, a batch of many, rows beyond the resident table (one
+    # launch per row window, each with its own counter and cursors) and long rows
     primes = wl.PRIMES_C2
     cb.cuboid_set_tuning(ctx, primes, workgroups=wg, schedule=schedule)
     try:
@@ -373,5 +373,5 @@ def test_both_work_schedules(ctx, schedule, wg):
 
 def test_schedule_out_of_range(ctx):
     with pytest.raises(cb.CuboidError) as e:
-        cb.cuboid_set_tuning(ctx, wl.PRIMES_C2, schedule=3)
+        cb.cuboid_set_tuning(ctx, wl.PRIMES_C2, schedule=4)
     assert e.value.status == cb.E_ARG

@@ -159,8 +159,8 @@ def test_section6_scan_against_the_oracle(ctx):
     assert g["max_depth_prime"] == 137
 
 
-@pytest.mark.parametrize("schedule", [1, 2])
-def test_region_under_both_work_schedules(ctx, schedule):
+@pytest.mark.parametrize("schedule", [1, 2, 3])
+def test_region_under_each_work_schedule(ctx, schedule):
     # the region scan of rows 1..4000 with primes 11..541 under each way of
     # sharing units between waves, against the default
     primes = wl.PRIMES_PAPER
@@ -170,6 +170,25 @@ def test_region_under_both_work_schedules(ctx, schedule):
         got = cb.cuboid_sieve_region(ctx, 1, 4000, primes, band_rows=100)
     finally:
         cb.cuboid_set_tuning(ctx, primes)
+    assert got["n_pairs"] == ref["n_pairs"]
+    assert [int(c) for c in got["counts"]] == [int(c) for c in ref["counts"]]
+    assert got["survivors"] == ref["survivors"]
+    assert [int(x) for x in got["r_max"]] == [int(x) for x in ref["r_max"]]
+
+
+def test_region_large_workgroup_pieces(ctx):
+    # rows 1..20000 on a grid of one workgroup: over 32 * 4096 units, so the
+    # workgroup's share comes in pieces of 4096 units; against round-robin
+    # pieces per wave on the full grid
+    primes = wl.PRIMES_PAPER
+    cb.cuboid_set_tuning(ctx, primes, schedule=1)
+    try:
+        ref = cb.cuboid_sieve_region(ctx, 1, 20000, primes, band_rows=100)
+        cb.cuboid_set_tuning(ctx, primes, schedule=3, workgroups=1)
+        got = cb.cuboid_sieve_region(ctx, 1, 20000, primes, band_rows=100)
+    finally:
+        cb.cuboid_set_tuning(ctx, primes)
+    assert ref["n_pairs"] > 32 * 4096 * 4096 // 2
     assert got["n_pairs"] == ref["n_pairs"]
     assert [int(c) for c in got["counts"]] == [int(c) for c in ref["counts"]]
     assert got["survivors"] == ref["survivors"]
