@@ -371,6 +371,26 @@ def test_work_schedules(ctx, schedule, wg):
         cb.cuboid_set_tuning(ctx, primes)
 
 
+@pytest.mark.parametrize("wg", [1, 7])
+def test_workgroup_pieces_large_and_odd_grids(ctx, wg):
+    # 129 row blocks x 1094 windows: on one workgroup more than 32 x 4096 units,
+    # so its share comes in pieces of 4096 units; on seven workgroups pieces of
+    # 256 units that do not divide evenly between them.  Against round-robin
+    # pieces per wave on the full grid.
+    primes = wl.PRIMES_C2
+    rect = (1, 8200, 1, 70000)
+    cb.cuboid_set_tuning(ctx, primes, schedule=1)
+    try:
+        ref = cb.cuboid_sieve_range(ctx, *rect, primes, cap=1 << 16)
+        cb.cuboid_set_tuning(ctx, primes, schedule=3, workgroups=wg)
+        got = cb.cuboid_sieve_range(ctx, *rect, primes, cap=1 << 16)
+    finally:
+        cb.cuboid_set_tuning(ctx, primes)
+    assert got["n_pairs"] == ref["n_pairs"] > 0
+    assert [int(c) for c in got["counts"]] == [int(c) for c in ref["counts"]]
+    assert [int(x) for x in got["survivors"]] == [int(x) for x in ref["survivors"]]
+
+
 def test_schedule_out_of_range(ctx):
     with pytest.raises(cb.CuboidError) as e:
         cb.cuboid_set_tuning(ctx, wl.PRIMES_C2, schedule=4)
