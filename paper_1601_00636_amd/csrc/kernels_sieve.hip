@@ -39,9 +39,19 @@ __device__ __forceinline__ uint64_t uni64(uint64_t v) {
     return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
 }
 
+// Sum over the wave with DPP moves (no LDS round trips): an inclusive scan
+// within each row of 16 lanes (row_shr 1, 2, 4, 8), then lane 15 of rows 0 and
+// 2 added into rows 1 and 3 (row_bcast:15) and lane 31 into rows 2 and 3
+// (row_bcast:31); lane 63 ends with the total.
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
+    int x = (int)v;
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return (uint32_t)__builtin_amdgcn_readlane(x, 63);
 }
 
 __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
@@ -409,7 +419,12 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
                 cup = false;
             }
             const uint32_t nf = (rinfo.meta >> 4) & 15;
-            const uint32_t nfmax = uni(wave_max(nf));
+            // the wave's largest factor count, from ballots (cross-lane
+            // shuffles go through the LDS pipe and cost a round trip each)
+            uint32_t nfmax = 0;
+    #pragma unroll
+            for (int f = 1; f <= MF; ++f)
+                if (__ballot(nf >= (uint32_t)f) != 0) nfmax = (uint32_t)f;
             const uint32_t wheel_lane = wheel_byte + (rinfo.meta & 15) * (kWheel * 8);
             const uint32_t qs = R.q0 + win0 * kWave;
             // columns of this lane's row: [q0, q1], cut to region (1.2) in a
@@ -423,8 +438,16 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
                 rhi = b < rhi ? b : rhi;
             }
             if (p == 1 && rlo < 2) rlo = 2;   // (1, 1) is coprime but p = q
-            const uint32_t lo_max = uni(wave_max(rlo));
-            const uint32_t hi_min = uni(wave_min(rhi));
+            // in a rectangle every lane has [q0, q1] but the row p = 1, which
+            // starts at 2: the wave's bounds need no reduction there
+            uint32_t lo_max, hi_min;
+            if (R.flags & kReqRegion) {
+                lo_max = uni(wave_max(rlo));
+                hi_min = uni(wave_min(rhi));
+            } else {
+                lo_max = (__ballot(p == 1) != 0 && R.q0 < 2) ? 2u : R.q0;
+                hi_min = R.q1;
+            }
             // a window starting above edge_hi reaches past hi_min; windows
             // k < k_lo start below lo_max and windows k >= k_hi reach past
             // hi_min: only those take the per-lane masks
