@@ -359,7 +359,7 @@ typedef struct cuboid_tuning {
 } cuboid_tuning;
 
 /*
- * Time candidate tunings for `primes` (the last five dense-prime counts that
+ * Time candidate tunings for `primes` (the last six dense-prime counts that
  * fit in LDS, times grids of 1, 2, 4 and 8 workgroups per compute unit) on a
  * sample rectangle of 32768 x 65536 pairs near 2^19 and keep the fastest for
  * this context; if cache_path is non-NULL the choice is read from
