@@ -197,8 +197,8 @@ def main():
         return calibrate_copy()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on exactly one GPU; --gpus %d is not supported "
-              "(the sieve would shard by row bands, see the design notes)" % args.gpus,
+        print("bench.py: the benchmark runs on exactly one GPU; --gpus %d is not supported "
+              "(across GPUs the sieve would shard by bands of rows p)" % args.gpus,
               file=sys.stderr)
         return 2
 
