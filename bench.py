@@ -24,12 +24,31 @@ import time
 import numpy as np
 
 METRIC = "coprime (p,q) pairs sieved/sec at 1 GPU, bit-exact; batched vs plain; p50/p99"
-INT32_PEAK = 256 * 64 * 2.4e9    # 256 CUs x 64 INT32 lane-ops per clock x 2.4 GHz
+# 256 CUs x 4 SIMDs x 16 lanes: 64 INT32 lane-operations per clock per CU, at 2.4 GHz
+INT32_PEAK = 256 * 64 * 2.4e9
+# LDS: 128 bytes per clock per CU
+LDS_PEAK = 256 * 128 * 2.4e9
+# VALU issue: one wave64 instruction every 4 cycles on each of 1024 SIMDs
+SIMDS, CLOCK = 1024, 2.4e9
+
+# Work model of the bit-sliced sweep, per lane and 64-column window (64 pairs
+# of one row p):
+#   wheel (2, 3, 5): step the window's wheel offset, complement the word   3
+#   each prime factor l >= 7 of p: its multiple pattern OR-ed in (2), the
+#     pattern index (1), the distance to the next multiple advanced (3)     6
+#   coprime-pair count: two 32-bit popcounts                                 2
+#   each dense prime: table address (1), AND-NOT (2), two popcounts (2)      5
+#   leftover test for the deep path (one 64-bit compare)                     1
+# and 10 lane-operations per deep lookup (two residues by multiply-high,
+# the inverse and ratio-vector reads, one modular product, the test).
+# LDS bytes per lane and window: 8 for the wheel word, 8 per factor >= 7,
+# 8 per dense prime.
+W_FIXED, W_FACTOR, W_DENSE, W_DEEP = 6, 6, 5, 10
 
 
-def omega_weighted(rects):
-    """Mean number of distinct prime factors of p over the raw pairs of the
-    rectangles (each row weighted by its column count)."""
+def omega_weighted(rects, least=2):
+    """Mean number of distinct prime factors >= least of p over the raw pairs
+    of the rectangles (each row weighted by its column count)."""
     pmax = max(r[1] for r in rects)
     is_p = np.ones(pmax + 1, dtype=bool)
     is_p[:2] = False
@@ -38,13 +57,71 @@ def omega_weighted(rects):
             is_p[i * i::i] = False
     omega = np.zeros(pmax + 1, dtype=np.int32)
     for ell in np.nonzero(is_p)[0]:
-        omega[ell::ell] += 1
+        if ell >= least:
+            omega[ell::ell] += 1
     num = den = 0.0
     for p0, p1, q0, q1 in rects:
         w = q1 - q0 + 1
         num += float(omega[p0:p1 + 1].sum()) * w
         den += float(p1 - p0 + 1) * w
     return num / den
+
+
+def deep_lookups(counts_total, n_surv, primes, trivial, k_dense):
+    """Table lookups the deep path makes: every pair that passes the first
+    k_dense non-trivial primes is tested against the later ones in ascending
+    order until one rejects it (all of them for a survivor)."""
+    order = np.argsort(primes)
+    k = 0
+    tot = 0
+    for i in order:
+        if trivial[i]:
+            continue
+        k += 1
+        if k > k_dense:
+            tot += (k - k_dense) * int(counts_total[i])
+    return tot + max(0, k - k_dense) * n_surv
+
+
+def sweep_work_model(rects, k_dense, deep):
+    """(VALU lane-operations, LDS bytes, units) of the work model for one
+    sweep over the rectangles: units = raw pairs / 4096, so ragged tiles at
+    request edges earn nothing."""
+    w7 = omega_weighted(rects, least=7)
+    raw = sum((p1 - p0 + 1) * (q1 - q0 + 1) for p0, p1, q0, q1 in rects)
+    units = raw / 4096.0
+    ops = 64 * units * (W_FIXED + W_FACTOR * w7 + W_DENSE * k_dense) + W_DEEP * deep
+    lds = 64 * units * 8 * (1 + w7 + k_dense)
+    return ops, lds, units, w7
+
+
+def measured_counters(units_live, sweep_s):
+    """VALU-issue and LDS-bandwidth fractions of the sweep from the committed
+    SQ counter record, only while the sweep kernel's source is the one the
+    counters were taken on: per-unit instruction counts times this launch's
+    units over its measured duration."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    try:
+        with open(os.path.join(here, "profiles", "sweep_counters.json")) as f:
+            rec = json.load(f)
+        with open(os.path.join(here, "paper_1601_00636_amd", "csrc", "kernels_sieve.hip"), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != sha:
+        return None
+    pu = rec["per_unit"]
+    valu = pu["SQ_INSTS_VALU"] * units_live
+    lds_inst = pu["SQ_INSTS_LDS"] * units_live
+    out = {"valu_insts_per_unit": pu["SQ_INSTS_VALU"],
+           "valu_issue_frac": valu * 4 / (SIMDS * CLOCK * sweep_s),
+           "lds_insts_per_unit": pu["SQ_INSTS_LDS"],
+           "lds_frac": lds_inst * 512 / sweep_s / LDS_PEAK,
+           "source": "profiles/sweep_counters.json"}
+    if pu.get("SQ_ACTIVE_INST_LDS"):
+        out["lds_bank_conflict_ratio"] = pu["SQ_LDS_BANK_CONFLICT"] / pu["SQ_ACTIVE_INST_LDS"]
+    return out
 
 
 def mean_depth(counts_total, n_surv, primes, trivial):
@@ -77,6 +154,28 @@ def measured_traffic():
     if rec.get("kernel_source_sha256") != sha:
         return None, None
     return rec["traffic_GBps"], rec["traffic_bytes_per_launch"]
+
+
+def verify_against_golden(req_arr, primes, counts, pairs, surv):
+    """The last timed step's per-request counts, pair counts and sorted
+    survivor lists against the oracle's for the same 4096 rectangles
+    (tests/golden/oracle_c4.npz, written by tests/golden/make_golden.py from
+    the oracle alone)."""
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "tests", "golden", "oracle_c4.npz")
+    if not os.path.exists(path):
+        return {"ok": None, "why": "oracle_c4.npz missing"}
+    g = np.load(path)
+    same_input = (np.array_equal(g["rects"].astype(np.int64), req_arr)
+                  and np.array_equal(g["primes"].astype(np.int64), np.asarray(primes)))
+    g_req = np.repeat(np.arange(len(g["n_survivors"]), dtype=np.int64),
+                      g["n_survivors"].astype(np.int64))
+    ok = (same_input and np.array_equal(g["counts"], counts) and np.array_equal(g["n_pairs"], pairs)
+          and np.array_equal(g_req, surv["req"].astype(np.int64))
+          and np.array_equal(g["survivors"], surv["idx"]))
+    return {"ok": bool(ok), "against": "tests/golden/oracle_c4.npz (oracle, all 4096 requests)",
+            "requests": int(len(pairs)), "coprime_pairs": int(pairs.sum()),
+            "survivors": int(len(surv))}
 
 
 def run_cpu_baseline(reqs, primes, stride):
@@ -274,17 +373,26 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     sweep_avg = float(np.mean(sweeps))
-    dev_counts, dev_pairs, _ = dev.read()
+    dev_counts, dev_pairs, dev_surv = dev.read()
 
     n_pairs = int(dev_pairs.sum())
     counts = dev_counts.sum(axis=0)
     value = n_pairs * args.steps / elapsed
+    verified = verify_against_golden(req_arr, primes, dev_counts, dev_pairs, dev_surv)
+    # the survey's scalar model: 4 D + 3 w + 1 INT32 operations per coprime pair
     lookups, k_nt = mean_depth(counts, nsurv, primes, trivial)
     dbar = lookups / n_pairs
     wbar = omega_weighted(reqs)
     ops_pair = 4 * dbar + 3 * wbar + 1
-    achieved = ops_pair * n_pairs / (sweep_avg * 1e-3)
+    scalar_achieved = ops_pair * n_pairs / (sweep_avg * 1e-3)
+    # the bit-sliced work model (per unit of 64 x 64 raw pairs)
+    k_dense = int(tim["dense_primes"])
+    deep = deep_lookups(counts, nsurv, primes, trivial, k_dense)
+    m_ops, m_lds, m_units, w7 = sweep_work_model(reqs, k_dense, deep)
+    achieved = m_ops / (sweep_avg * 1e-3)
+    lds_achieved = m_lds / (sweep_avg * 1e-3)
     traffic_gbps, traffic_bytes = measured_traffic()
+    ctr = measured_counters(tim["units"], sweep_avg * 1e-3)
 
     res = {
         "metric": METRIC,
@@ -306,15 +414,28 @@ def main():
                    "tuning": tun},
         "extras": {},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT32_PEAK / 1e12,
-                     "unit": "Tops/s (INT32)", "frac": achieved / INT32_PEAK, "traffic": traffic_gbps,
+                     "unit": "T lane-ops/s (INT32 VALU)", "frac": achieved / INT32_PEAK,
+                     "traffic": traffic_gbps,
                      "traffic_unit": "GB/s HBM (FETCH_SIZE, WRITE_SIZE scaled by a 1 GiB copy)",
                      "traffic_bytes_per_launch": traffic_bytes,
                      "kernel": "sweep_kernel", "sweep_ms": sweep_avg,
-                     "ops_per_pair": ops_pair, "mean_lookups": dbar, "mean_omega": wbar,
-                     "units_64x64": tim["units"],
-                     "note": "achieved counts the method's scalar INT32 operations per "
-                             "coprime pair (4 D + 3 w + 1); the bit-sliced sweep does 64 "
-                             "pairs per lane operation, so frac exceeds 1"},
+                     "model": "per lane and 64-column window: %d + %d per factor >= 7 of p + "
+                              "%d per dense prime VALU lane-ops, 8 LDS bytes per word read "
+                              "(wheel, factors, dense primes); %d lane-ops per deep lookup"
+                              % (W_FIXED, W_FACTOR, W_DENSE, W_DEEP),
+                     "units_64x64_raw": m_units, "units_64x64_launched": tim["units"],
+                     "dense_primes": k_dense, "mean_factors_ge7": w7, "deep_lookups": deep,
+                     "lane_ops_per_launch": m_ops,
+                     "lds": {"achieved": lds_achieved / 1e12, "peak": LDS_PEAK / 1e12,
+                             "unit": "TB/s", "frac": lds_achieved / LDS_PEAK,
+                             "bytes_per_launch": m_lds},
+                     "counters": ctr,
+                     "model_frac": scalar_achieved / INT32_PEAK,
+                     "model_frac_note": "the survey's scalar model, 4 D + 3 w + 1 INT32 "
+                                        "operations per coprime pair (D = %.4f lookups, w = "
+                                        "%.4f factors): the bit-sliced sweep covers 64 pairs "
+                                        "per lane operation, so it exceeds 1" % (dbar, wbar)},
+        "verified": verified,
     }
 
     res["config"]["launch"] = {0: "call by call", 1: "hip graph replay",
@@ -423,8 +544,9 @@ def main():
                                            "value": rd["n_pairs"] / dt}
         # measured throughputs of the two units that bound the sweep
         pk = cb.cuboid_probe_peaks(ctx)
-        res["extras"]["measured_peaks"] = dict(pk, sweep_lane_ops_frac_of_measured=(
-            res["roofline"]["achieved"] * 1e12 / pk["valu_lane_ops_per_s"]))
+        res["extras"]["measured_peaks"] = pk
+        res["roofline"]["frac_of_measured_peak"] = achieved / pk["valu_lane_ops_per_s"]
+        res["roofline"]["lds"]["frac_of_measured_peak"] = lds_achieved / pk["lds_bytes_per_s"]
 
     if not args.no_extras and args.served_seconds > 0:
         res["extras"]["served"] = run_served(cb, wl, ctx, primes, args.served_seconds)

@@ -56,6 +56,13 @@ typedef enum cuboid_status {
     CUBOID_E_DATA = 10        /* file contents differ from the tables they name   */
 } cuboid_status;
 
+/*
+ * A context handle is an opaque token, not an address: it names a slot of the
+ * library's context table and the generation of that slot, so the handle of
+ * a destroyed context is refused (E_NOT_LOADED) for the rest of the process,
+ * even after new contexts are created.  Every call holds its context for its
+ * whole length; cuboid_destroy returns E_BUSY meanwhile.
+ */
 typedef struct cuboid_ctx cuboid_ctx;
 
 /* Short English text for a status code (static storage). */
@@ -69,14 +76,16 @@ const char *cuboid_version(void);
  * tables (small-prime list, coprimality wheel).  Unsolvability tables are
  * built on the GPU the first time a prime set is used and then stay resident
  * (the analogue of the paper's Load_Cuboid_Binaries, section 4).
- * Errors: E_ARG (out == NULL), E_DEVICE (no device / not gfx950 / HIP error).
+ * Errors: E_ARG (out == NULL), E_DEVICE (no device / not gfx950 / HIP error),
+ * E_LIMIT (4096 contexts alive at once).
  */
 int cuboid_create(cuboid_ctx **out, int hip_device);
 
 /*
  * Destroy a context and free its device memory (cf. Release_Cuboid_Binaries,
- * section 5).  Returns E_BUSY, destroying nothing, while a call or a server
- * is still using it; E_NOT_LOADED for NULL.
+ * section 5).  Returns E_BUSY, destroying nothing, while a call (running or
+ * waiting for the context), a server or a search is still using it;
+ * E_NOT_LOADED for NULL, a destroyed context or any other value.
  */
 int cuboid_destroy(cuboid_ctx *ctx);
 
@@ -164,7 +173,10 @@ int cuboid_sieve_region(cuboid_ctx *ctx, uint32_t p0, uint32_t p1, uint32_t band
  */
 typedef struct cuboid_root {
     uint32_t p, q;
-    uint64_t t;
+    uint64_t t;             /* the root t = t_hi 2^64 + t: low 64 bits       */
+    uint64_t t_hi;          /* high bits (candidates reach about 2^66.5 for  */
+                            /* p, q near 2^32; every root found so far,       */
+                            /* t = p^2 for p = q or q = 0, is below 2^64)     */
     uint32_t flags;
     uint32_t input_index;   /* position of (p, q) in the input arrays */
 } cuboid_root;
@@ -177,27 +189,34 @@ typedef struct cuboid_root {
  * p^5 q^5 up to a root bound; each candidate is evaluated modulo three 62-bit
  * primes.  CPU part: candidates that vanish modulo all three are confirmed in
  * exact multiprecision arithmetic.  Roots are listed by input index, then by t.
- * p[i], q[i] < 2^31 (so every root is below 2^64).  p[i] = q[i] = 0 has no
+ * Any p[i], q[i] < 2^32 (the sieve's whole coordinate range, up to q = 59 p
+ * at the paper's p_max, sections 5-6): the root bound on t is then below
+ * 2^67, and candidates are carried in 128 bits.  p[i] = q[i] = 0 has no
  * positive roots.
- * Errors: E_LIMIT (a coordinate >= 2^31, or more than 2^40 candidates for one
- * pair), E_CAPACITY (*n_roots set to the number needed), E_ARG, E_DEVICE.
+ * Errors: E_LIMIT (more than 2^40 candidates for one pair), E_CAPACITY
+ * (*n_roots set to the number needed), E_ARG, E_DEVICE, E_NOT_LOADED.
  */
 int cuboid_root_check(cuboid_ctx *ctx, const uint32_t *p, const uint32_t *q, uint64_t n,
                       cuboid_root *roots, uint64_t cap, uint64_t *n_roots);
 
 /*
  * Exact CPU confirmation alone (no GPU): *is_root = 1 iff Q_pq(t) == 0 in
- * exact integer arithmetic; *flags as in cuboid_root.  p, q < 2^31.
- * Errors: E_ARG, E_LIMIT.
+ * exact integer arithmetic, for t = t_hi 2^64 + t_lo; *flags as in
+ * cuboid_root.  Any p, q < 2^32; t < 2^70.
+ * Errors: E_ARG, E_LIMIT (t >= 2^70).
  */
-int cuboid_exact_check(uint32_t p, uint32_t q, uint64_t t, int *is_root, uint32_t *flags);
+int cuboid_exact_check(uint32_t p, uint32_t q, uint64_t t_lo, uint64_t t_hi, int *is_root,
+                       uint32_t *flags);
 
 /*
- * Q_pq(t) in exact integer arithmetic on the CPU, as a signed decimal string
- * with its terminating NUL (for checking the exact arithmetic).  p, q < 2^31.
- * Errors: E_ARG, E_LIMIT, E_CAPACITY (cap too small for the string).
+ * Q_pq(t) in exact integer arithmetic on the CPU, t = t_hi 2^64 + t_lo, as a
+ * signed decimal string with its terminating NUL (for checking the exact
+ * arithmetic).  Any p, q < 2^32; t < 2^70.
+ * Errors: E_ARG, E_LIMIT (t >= 2^70), E_CAPACITY (cap too small for the
+ * string).
  */
-int cuboid_exact_value(uint32_t p, uint32_t q, uint64_t t, char *out, size_t cap);
+int cuboid_exact_value(uint32_t p, uint32_t q, uint64_t t_lo, uint64_t t_hi, char *out,
+                       size_t cap);
 
 /*
  * Prime-list canonicalisation alone (no GPU): validates `primes` and writes

@@ -2,10 +2,16 @@
 (include/cuboid.h).  Argument marshalling only: every step of the sieve runs in
 the library's HIP kernels.  Raises CuboidError for non-zero status codes.
 
-Streams: None (the context's own stream) or a raw hipStream_t integer created
-by the HIP runtime the library links (/opt/rocm); torch's default stream maps to
-None, other torch streams are refused (torch wheels carry a HIP runtime of
-their own).
+One HIP runtime per process: PyTorch wheels ship a HIP runtime of their own
+(torch/lib/libamdhip64.so, with the same soname libamdhip64.so.7 as
+/opt/rocm's).  The library is loaded after torch whenever torch is importable,
+so its libamdhip64.so.7 dependency is satisfied by the copy torch has already
+mapped and the two share devices, streams and memory; loading fails if two
+HIP runtimes are mapped anyway.  Without torch the library uses /opt/rocm's.
+
+Streams: None (the context's own stream), a raw hipStream_t integer, or a
+torch.cuda.Stream (its handle).  Device buffers: integer addresses, or torch
+device tensors passed by data_ptr() (TensorBatch).
 """
 import ctypes
 import os
@@ -23,7 +29,8 @@ P = ctypes.POINTER
 
 
 class cuboid_root(ctypes.Structure):
-    _fields_ = [("p", u32), ("q", u32), ("t", u64), ("flags", u32), ("input_index", u32)]
+    _fields_ = [("p", u32), ("q", u32), ("t", u64), ("t_hi", u64), ("flags", u32),
+                ("input_index", u32)]
 
 
 class cuboid_request(ctypes.Structure):
@@ -79,13 +86,35 @@ class CuboidError(RuntimeError):
 _lib = None
 
 
+def hip_runtimes():
+    """Paths of the HIP runtime libraries (libamdhip64) mapped into this process."""
+    found = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                path = line.split()[-1] if line.count("/") else ""
+                if os.path.basename(path).startswith("libamdhip64"):
+                    found.add(os.path.realpath(path))
+    except OSError:
+        pass
+    return sorted(found)
+
+
 def _load():
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError("libcuboid.so is not built (run paper_1601_00636_amd.build.build())")
+    try:
+        import torch  # noqa: F401  (maps torch's HIP runtime before the library's dependency)
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
+    runtimes = hip_runtimes()
+    if len(runtimes) > 1:
+        raise ImportError("two HIP runtimes are mapped (%s): load libcuboid after torch, or "
+                          "without it" % ", ".join(runtimes))
     vp = ctypes.c_void_p
     sigs = {
         "cuboid_status_string": ([i32], ctypes.c_char_p),
@@ -99,8 +128,8 @@ def _load():
         "cuboid_sieve_region": ([vp, u32, u32, u32, P(u32), u32, P(u64), u64, P(u64), P(u64),
                                  P(u64), P(u32), vp], i32),
         "cuboid_root_check": ([vp, P(u32), P(u32), u64, P(cuboid_root), u64, P(u64)], i32),
-        "cuboid_exact_check": ([u32, u32, u64, P(i32), P(u32)], i32),
-        "cuboid_exact_value": ([u32, u32, u64, ctypes.c_char_p, ctypes.c_size_t], i32),
+        "cuboid_exact_check": ([u32, u32, u64, u64, P(i32), P(u32)], i32),
+        "cuboid_exact_value": ([u32, u32, u64, u64, ctypes.c_char_p, ctypes.c_size_t], i32),
         "cuboid_canonical_primes": ([P(u32), u32, P(u32), P(u8)], i32),
         "cuboid_sieve_batch": ([vp, P(cuboid_request), u32, P(u32), u32, P(cuboid_result), vp], i32),
         "cuboid_sieve_batch_dev": ([vp, P(cuboid_request), u32, P(u32), u32, vp, vp, vp, u64,
@@ -161,19 +190,21 @@ def _p(a, ct):
 
 
 def _stream(stream):
-    """None (the context's stream), or a raw hipStream_t of the HIP runtime the
-    library is linked against.  PyTorch wheels carry their own HIP runtime, so
-    a torch stream other than its default (null) one is not a stream of the
-    library's runtime and is refused."""
+    """None (the context's stream), a raw hipStream_t, or a torch stream, whose
+    handle is a stream of the same HIP runtime (see the module docstring).
+    torch's default stream is the null stream, handle 0, which the C interface
+    reads as the context's own stream: work already queued on it is waited
+    for first, so the call still comes after it (every call returns
+    synchronised)."""
     if stream is None:
         return None
     if isinstance(stream, int):
         return ctypes.c_void_p(stream) if stream else None
     handle = int(stream.cuda_stream)
-    if handle:
-        raise ValueError("a torch stream belongs to torch's own HIP runtime; pass None or a "
-                         "hipStream_t created by the library's runtime")
-    return None
+    if not handle:
+        stream.synchronize()
+        return None
+    return ctypes.c_void_p(handle)
 
 
 def _check(st, what, needed=None):
@@ -313,19 +344,28 @@ def cuboid_root_check(ctx, p, q, cap=1 << 16):
     st = _load().cuboid_root_check(ctx, _p(p, u32), _p(q, u32), len(p), roots, int(cap),
                                    ctypes.byref(n))
     _check(st, "cuboid_root_check", needed=n.value if st == E_CAPACITY else None)
-    return [(r.p, r.q, r.t, r.flags, r.input_index) for r in roots[:n.value]]
+    return [(r.p, r.q, r.t | r.t_hi << 64, r.flags, r.input_index) for r in roots[:n.value]]
+
+
+def _t_halves(t):
+    t = int(t)
+    if t < 0 or t >= 1 << 128:
+        raise ValueError("t must be in [0, 2^128)")
+    return t & ((1 << 64) - 1), t >> 64
 
 
 def cuboid_exact_check(p, q, t):
     z, f = i32(0), u32(0)
-    _check(_load().cuboid_exact_check(int(p), int(q), int(t), ctypes.byref(z), ctypes.byref(f)),
+    lo, hi = _t_halves(t)
+    _check(_load().cuboid_exact_check(int(p), int(q), lo, hi, ctypes.byref(z), ctypes.byref(f)),
            "cuboid_exact_check")
     return bool(z.value), f.value
 
 
 def cuboid_exact_value(p, q, t):
     buf = ctypes.create_string_buffer(1024)
-    _check(_load().cuboid_exact_value(int(p), int(q), int(t), buf, 1024), "cuboid_exact_value")
+    lo, hi = _t_halves(t)
+    _check(_load().cuboid_exact_value(int(p), int(q), lo, hi, buf, 1024), "cuboid_exact_value")
     return int(buf.value.decode())
 
 
@@ -438,9 +478,50 @@ class DeviceBatch:
                 setattr(self, a, 0)
 
 
+class TensorBatch:
+    """cuboid_sieve_batch_dev's outputs in caller-owned torch device tensors,
+    passed by data_ptr(): counts [n_req, n_primes] and pairs [n_req], int64 or
+    uint64; survivors int64 or uint64 [surv_cap, 2] (row k: the pair index and
+    the request number), or None.  read() returns numpy copies as
+    DeviceBatch.read() does."""
+
+    def __init__(self, counts, pairs, survivors=None):
+        def check(t, name, ndim):
+            if not t.is_cuda or not t.is_contiguous() or t.element_size() != 8 or t.dim() != ndim:
+                raise ValueError("%s: a contiguous 64-bit integer device tensor of %d dims"
+                                 % (name, ndim))
+        check(counts, "counts", 2)
+        check(pairs, "pairs", 1)
+        if counts.shape[0] != pairs.shape[0]:
+            raise ValueError("counts and pairs disagree on the number of requests")
+        self.n_req, self.n_primes = int(counts.shape[0]), int(counts.shape[1])
+        self.tensors = (counts, pairs, survivors)
+        self.counts, self.pairs = counts.data_ptr(), pairs.data_ptr()
+        self.surv, self.surv_cap = 0, 0
+        if survivors is not None:
+            check(survivors, "survivors", 2)
+            if survivors.shape[1] != 2:
+                raise ValueError("survivors: shape [surv_cap, 2]")
+            self.surv, self.surv_cap = survivors.data_ptr(), int(survivors.shape[0])
+        self.n_survivors = 0
+
+    def read(self):
+        counts, pairs, survivors = self.tensors
+        c = counts.cpu().numpy().view(np.uint64)
+        p = pairs.cpu().numpy().view(np.uint64)
+        k = min(self.n_survivors, self.surv_cap)
+        if k:
+            raw = survivors[:k].cpu().numpy()
+            surv = np.ascontiguousarray(raw).view(_SURV_DEV_DTYPE).reshape(k)
+        else:
+            surv = np.empty(0, dtype=_SURV_DEV_DTYPE)
+        return c, p, surv
+
+
 def cuboid_sieve_batch_dev(ctx, requests, primes, dev, stream=None):
-    """requests: (n, 4) array-like of (p0, p1, q0, q1); dev: a DeviceBatch of
-    the same n and prime count.  Returns the status; dev.n_survivors is set."""
+    """requests: (n, 4) array-like of (p0, p1, q0, q1); dev: a DeviceBatch or
+    TensorBatch of the same n and prime count.  Returns the status;
+    dev.n_survivors is set."""
     pr = _arr(primes, np.uint32)
     reqa = np.ascontiguousarray(np.asarray(requests, dtype=np.uint32).reshape(-1, 4))
     n = reqa.shape[0]

@@ -17,20 +17,57 @@ using namespace cuboid;
 
 namespace {
 
-// every live context, so that calls on destroyed or foreign pointers are refused
+// Handles given to callers are opaque tokens, not addresses: a slot of the
+// table below and the generation the slot had when the context was created
+// there.  A handle of a destroyed context never matches again (its slot's
+// generation has moved on), so stale handles are refused even when a new
+// context reuses the slot or the old context's memory.  Every entry point
+// holds a reference on the context for the length of the call (CtxRef); it
+// is taken under g_ctx_mu while the context is in the table, and
+// cuboid_destroy removes the context under the same lock only when no
+// reference is held, so a call can never see its context freed under it.
+constexpr uint32_t kSlots = 4096;
+struct Slot {
+    cuboid_ctx *ctx = nullptr;
+    uint32_t gen = 0;
+    uint32_t refs = 0;
+};
 std::mutex g_ctx_mu;
-std::vector<cuboid_ctx *> g_ctxs;
+Slot g_slots[kSlots];
 
-bool ctx_live(cuboid_ctx *ctx) {
-    if (!ctx) return false;
-    std::lock_guard<std::mutex> g(g_ctx_mu);
-    return std::find(g_ctxs.begin(), g_ctxs.end(), ctx) != g_ctxs.end();
+uintptr_t make_handle(uint32_t slot, uint32_t gen) {
+    return ((uintptr_t)gen << 16 | (slot + 1)) << 4;
+}
+
+Slot *find_slot(cuboid_ctx *handle) {   // under g_ctx_mu
+    const uintptr_t h = (uintptr_t)handle;
+    if (!h || (h & 15)) return nullptr;
+    const uint32_t slot = (uint32_t)((h >> 4) & 0xffff);
+    if (slot == 0 || slot > kSlots) return nullptr;
+    Slot &s = g_slots[slot - 1];
+    if (!s.ctx || make_handle(slot - 1, s.gen) != h) return nullptr;
+    return &s;
 }
 
 }  // namespace
 
 namespace cuboid {
-bool ctx_is_live(cuboid_ctx *ctx) { return ctx_live(ctx); }
+
+CtxRef::CtxRef(cuboid_ctx *handle) {
+    std::lock_guard<std::mutex> g(g_ctx_mu);
+    Slot *s = find_slot(handle);
+    if (!s) return;
+    ++s->refs;
+    ctx_ = s->ctx;
+    slot_ = (uint32_t)(s - g_slots);
+}
+
+CtxRef::~CtxRef() {
+    if (!ctx_) return;
+    std::lock_guard<std::mutex> g(g_ctx_mu);
+    --g_slots[slot_].refs;
+}
+
 }  // namespace cuboid
 
 namespace {
@@ -114,30 +151,39 @@ int cuboid_create(cuboid_ctx **out, int hip_device) {
         free_ctx(ctx);
         return st;
     }
-    {
-        std::lock_guard<std::mutex> g(g_ctx_mu);
-        g_ctxs.push_back(ctx);
+    std::lock_guard<std::mutex> g(g_ctx_mu);
+    for (uint32_t i = 0; i < kSlots; ++i) {
+        Slot &s = g_slots[i];
+        if (s.ctx) continue;
+        s.gen = (s.gen + 1) & 0xffffffu;   // 24 bits of generation per slot
+        s.ctx = ctx;
+        s.refs = 0;
+        *out = (cuboid_ctx *)make_handle(i, s.gen);
+        return CUBOID_OK;
     }
-    *out = ctx;
-    return CUBOID_OK;
+    free_ctx(ctx);
+    return CUBOID_E_LIMIT;
 }
 
-int cuboid_destroy(cuboid_ctx *ctx) {
-    if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
-    if (ctx->servers.load() > 0 || ctx->searches.load() > 0) return CUBOID_E_BUSY;
-    if (!ctx->mu.try_lock()) return CUBOID_E_BUSY;
+int cuboid_destroy(cuboid_ctx *handle) {
+    cuboid_ctx *ctx = nullptr;
     {
         std::lock_guard<std::mutex> g(g_ctx_mu);
-        g_ctxs.erase(std::find(g_ctxs.begin(), g_ctxs.end(), ctx));
+        Slot *s = find_slot(handle);
+        if (!s) return CUBOID_E_NOT_LOADED;
+        ctx = s->ctx;
+        // a call in progress (or waiting for the context), a server or a search
+        if (s->refs > 0 || ctx->servers.load() > 0 || ctx->searches.load() > 0)
+            return CUBOID_E_BUSY;
+        s->ctx = nullptr;   // no new reference can be taken from here on
     }
-    ctx->mu.unlock();
     free_ctx(ctx);
     return CUBOID_OK;
 }
 
 int cuboid_q_mod_prime(cuboid_ctx *ctx, const uint32_t *p, const uint32_t *q, const uint32_t *t,
                        const uint32_t *r, uint64_t n, uint32_t *out) {
-    if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
+    CTX_ENTER(ctx);
     if (n == 0) return CUBOID_OK;
     if (!p || !q || !t || !r || !out) return CUBOID_E_ARG;
     for (uint64_t i = 0; i < n; ++i)
@@ -159,7 +205,7 @@ int cuboid_q_mod_prime(cuboid_ctx *ctx, const uint32_t *p, const uint32_t *q, co
 }
 
 int cuboid_table_bytes(cuboid_ctx *ctx, uint32_t r, uint8_t *out, size_t cap, size_t *written) {
-    if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
+    CTX_ENTER(ctx);
     if (!written) return CUBOID_E_ARG;
     if (r >= 65536 || !is_prime_u32(r)) return CUBOID_E_PRIMES;
     const size_t nbytes = ((size_t)r * r + 7) / 8;
@@ -185,7 +231,7 @@ int cuboid_sieve_range(cuboid_ctx *ctx, uint32_t p0, uint32_t p1, uint32_t q0, u
                        const uint32_t *primes, uint32_t n_primes, uint64_t *survivors,
                        uint64_t cap, uint64_t *n_survivors, uint64_t *counts, uint64_t *n_pairs,
                        void *hip_stream) {
-    if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
+    CTX_ENTER(ctx);
     if (!n_survivors || !counts || !n_pairs || (cap && !survivors)) return CUBOID_E_ARG;
     int st = rect_valid(p0, p1, q0, q1);
     if (st) return st;
@@ -213,7 +259,7 @@ int cuboid_sieve_region(cuboid_ctx *ctx, uint32_t p0, uint32_t p1, uint32_t band
                         const uint32_t *primes, uint32_t n_primes, uint64_t *survivors,
                         uint64_t cap, uint64_t *n_survivors, uint64_t *counts, uint64_t *n_pairs,
                         uint32_t *r_max, void *hip_stream) {
-    if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
+    CTX_ENTER(ctx);
     if (!n_survivors || !counts || !n_pairs || (cap && !survivors) || band_rows == 0)
         return CUBOID_E_ARG;
     if (p0 == 0 || p0 > p1) return CUBOID_E_RANGE;
@@ -232,7 +278,7 @@ int cuboid_sieve_region(cuboid_ctx *ctx, uint32_t p0, uint32_t p1, uint32_t band
 int cuboid_sieve_batch(cuboid_ctx *ctx, const cuboid_request *req, uint32_t n_req,
                        const uint32_t *primes, uint32_t n_primes, cuboid_result *res,
                        void *hip_stream) {
-    if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
+    CTX_ENTER(ctx);
     if (!req || !res || n_req == 0 || n_req == 0xffffffffu) return CUBOID_E_ARG;
     int bad = 0;
     uint64_t cap_total = 0;
@@ -298,7 +344,7 @@ int cuboid_sieve_batch_dev(cuboid_ctx *ctx, const cuboid_request *req, uint32_t 
                            const uint32_t *primes, uint32_t n_primes, uint64_t *counts_dev,
                            uint64_t *pairs_dev, void *survivors_dev, uint64_t surv_cap,
                            uint64_t *n_survivors, void *hip_stream) {
-    if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
+    CTX_ENTER(ctx);
     if (!req || n_req == 0 || n_req == 0xffffffffu || !counts_dev || !pairs_dev || !n_survivors ||
         (surv_cap && !survivors_dev))
         return CUBOID_E_ARG;
@@ -335,7 +381,7 @@ int cuboid_sieve_batch_dev(cuboid_ctx *ctx, const cuboid_request *req, uint32_t 
 int cuboid_device_alloc(cuboid_ctx *ctx, size_t bytes, void **out) {
     if (!out) return CUBOID_E_ARG;
     *out = nullptr;
-    if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
+    CTX_ENTER(ctx);
     if (bytes == 0) return CUBOID_E_ARG;
     CtxLock g(ctx);
     if (set_device(ctx)) return CUBOID_E_DEVICE;
@@ -343,7 +389,7 @@ int cuboid_device_alloc(cuboid_ctx *ctx, size_t bytes, void **out) {
 }
 
 int cuboid_device_free(cuboid_ctx *ctx, void *p) {
-    if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
+    CTX_ENTER(ctx);
     if (!p) return CUBOID_OK;
     CtxLock g(ctx);
     if (set_device(ctx)) return CUBOID_E_DEVICE;
@@ -354,7 +400,7 @@ int cuboid_device_free(cuboid_ctx *ctx, void *p) {
 
 int cuboid_device_read(cuboid_ctx *ctx, void *dst, const void *src_dev, size_t bytes,
                        void *hip_stream) {
-    if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
+    CTX_ENTER(ctx);
     if (bytes && (!dst || !src_dev)) return CUBOID_E_ARG;
     if (!bytes) return CUBOID_OK;
     CtxLock g(ctx);
@@ -367,7 +413,7 @@ int cuboid_device_read(cuboid_ctx *ctx, void *dst, const void *src_dev, size_t b
 
 int cuboid_probe_peaks(cuboid_ctx *ctx, double *valu_lane_ops_per_s, double *lds_bytes_per_s) {
     if (!valu_lane_ops_per_s || !lds_bytes_per_s) return CUBOID_E_ARG;
-    if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
+    CTX_ENTER(ctx);
     CtxLock g(ctx);
     if (set_device(ctx)) return CUBOID_E_DEVICE;
     return run_peak_probes(ctx->cu_count, ctx->stream, valu_lane_ops_per_s, lds_bytes_per_s) ==
@@ -389,22 +435,22 @@ int cuboid_canonical_primes(const uint32_t *primes, uint32_t n, uint32_t *sorted
     return CUBOID_OK;
 }
 
-int cuboid_exact_check(uint32_t p, uint32_t q, uint64_t t, int *is_root, uint32_t *flags) {
+int cuboid_exact_check(uint32_t p, uint32_t q, uint64_t t_lo, uint64_t t_hi, int *is_root,
+                       uint32_t *flags) {
     if (!is_root || !flags) return CUBOID_E_ARG;
-    if (p >= (1u << 31) || q >= (1u << 31)) return CUBOID_E_LIMIT;
     bool ok = true;
-    const bool z = exact_is_root(p, q, t, &ok);
+    const bool z = exact_is_root(p, q, t_lo, t_hi, &ok);
     if (!ok) return CUBOID_E_LIMIT;
     *is_root = z ? 1 : 0;
-    *flags = theorem_flags(p, q, t);
+    *flags = theorem_flags(p, q, t_lo, t_hi);
     return CUBOID_OK;
 }
 
-int cuboid_exact_value(uint32_t p, uint32_t q, uint64_t t, char *out, size_t cap) {
+int cuboid_exact_value(uint32_t p, uint32_t q, uint64_t t_lo, uint64_t t_hi, char *out,
+                       size_t cap) {
     if (!out) return CUBOID_E_ARG;
-    if (p >= (1u << 31) || q >= (1u << 31)) return CUBOID_E_LIMIT;
     std::string v;
-    if (!exact_value_decimal(p, q, t, &v)) return CUBOID_E_LIMIT;
+    if (!exact_value_decimal(p, q, t_lo, t_hi, &v)) return CUBOID_E_LIMIT;
     if (v.size() + 1 > cap) return CUBOID_E_CAPACITY;
     memcpy(out, v.c_str(), v.size() + 1);
     return CUBOID_OK;
@@ -412,13 +458,11 @@ int cuboid_exact_value(uint32_t p, uint32_t q, uint64_t t, char *out, size_t cap
 
 int cuboid_root_check(cuboid_ctx *ctx, const uint32_t *p, const uint32_t *q, uint64_t n,
                       cuboid_root *roots, uint64_t cap, uint64_t *n_roots) {
-    if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
+    CTX_ENTER(ctx);
     if (!n_roots || (n && (!p || !q)) || (cap && !roots)) return CUBOID_E_ARG;
     *n_roots = 0;
     if (n == 0) return CUBOID_OK;
     if (n >= (1ull << 32)) return CUBOID_E_LIMIT;
-    for (uint64_t i = 0; i < n; ++i)
-        if (p[i] >= (1u << 31) || q[i] >= (1u << 31)) return CUBOID_E_LIMIT;
     CtxLock g(ctx);
     if (set_device(ctx)) return CUBOID_E_DEVICE;
     hipStream_t s = ctx->stream;
@@ -468,18 +512,19 @@ int cuboid_root_check(cuboid_ctx *ctx, const uint32_t *p, const uint32_t *q, uin
     for (const RootHit &h : hits) {
         const RootCand &c = cand[h.cand];
         bool ok = true;
-        if (!exact_is_root(c.p, c.q, h.t, &ok)) {
+        if (!exact_is_root(c.p, c.q, h.t_lo, h.t_hi, &ok)) {
             if (!ok) return CUBOID_E_LIMIT;
             continue;
         }
         cuboid_root r;
-        r.p = c.p; r.q = c.q; r.t = h.t;
-        r.flags = theorem_flags(c.p, c.q, h.t);
+        r.p = c.p; r.q = c.q; r.t = h.t_lo; r.t_hi = h.t_hi;
+        r.flags = theorem_flags(c.p, c.q, h.t_lo, h.t_hi);
         r.input_index = h.cand;
         found.push_back(r);
     }
     std::sort(found.begin(), found.end(), [](const cuboid_root &a, const cuboid_root &b) {
-        return a.input_index < b.input_index || (a.input_index == b.input_index && a.t < b.t);
+        if (a.input_index != b.input_index) return a.input_index < b.input_index;
+        return a.t_hi < b.t_hi || (a.t_hi == b.t_hi && a.t < b.t);
     });
     *n_roots = found.size();
     if (found.size() > cap) return CUBOID_E_CAPACITY;
@@ -488,14 +533,14 @@ int cuboid_root_check(cuboid_ctx *ctx, const uint32_t *p, const uint32_t *q, uin
 }
 
 int cuboid_enable_timing(cuboid_ctx *ctx, int on) {
-    if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
+    CTX_ENTER(ctx);
     CtxLock g(ctx);
     ctx->timing = on != 0;
     return CUBOID_OK;
 }
 
 int cuboid_enable_graphs(cuboid_ctx *ctx, int on) {
-    if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
+    CTX_ENTER(ctx);
     CtxLock g(ctx);
     if (set_device(ctx)) return CUBOID_E_DEVICE;
     ctx->use_graphs = on != 0;
@@ -504,7 +549,7 @@ int cuboid_enable_graphs(cuboid_ctx *ctx, int on) {
 }
 
 int cuboid_last_timing(cuboid_ctx *ctx, cuboid_timing *out) {
-    if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
+    CTX_ENTER(ctx);
     if (!out) return CUBOID_E_ARG;
     CtxLock g(ctx);
     *out = ctx->last;
@@ -513,7 +558,7 @@ int cuboid_last_timing(cuboid_ctx *ctx, cuboid_timing *out) {
 
 int cuboid_set_tuning(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes,
                       const cuboid_tuning *tuning) {
-    if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
+    CTX_ENTER(ctx);
     std::vector<uint32_t> sorted;
     int st = canonical_primes(primes, n_primes, &sorted);
     if (st) return st;
@@ -528,7 +573,7 @@ int cuboid_set_tuning(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes
 
 int cuboid_get_tuning(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes,
                       cuboid_tuning *out) {
-    if (!ctx_live(ctx)) return CUBOID_E_NOT_LOADED;
+    CTX_ENTER(ctx);
     if (!out) return CUBOID_E_ARG;
     std::vector<uint32_t> sorted;
     int st = canonical_primes(primes, n_primes, &sorted);

@@ -140,7 +140,7 @@ uint64_t sample_hash(const cuboid_request *r, uint32_t n) {
 
 extern "C" int cuboid_autotune(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes,
                                const char *cache_path, cuboid_tuning *out) {
-    if (!ctx_is_live(ctx)) return CUBOID_E_NOT_LOADED;
+    CTX_ENTER(ctx);
     std::vector<uint32_t> sorted;
     int st = canonical_primes(primes, n_primes, &sorted);
     if (st) return st;
@@ -158,7 +158,7 @@ extern "C" int cuboid_autotune(cuboid_ctx *ctx, const uint32_t *primes, uint32_t
 extern "C" int cuboid_autotune_for(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes,
                                    const cuboid_request *sample, uint32_t n_sample,
                                    const char *cache_path, cuboid_tuning *out) {
-    if (!ctx_is_live(ctx)) return CUBOID_E_NOT_LOADED;
+    CTX_ENTER(ctx);
     if (!sample || n_sample == 0 || n_sample == 0xffffffffu) return CUBOID_E_ARG;
     for (uint32_t i = 0; i < n_sample; ++i)
         if (rect_valid(sample[i].p0, sample[i].p1, sample[i].q0, sample[i].q1))

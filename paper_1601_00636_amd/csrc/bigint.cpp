@@ -1,7 +1,8 @@
 // Exact confirmation of integer roots on the CPU: Q_pq(t) of eq. (1.1) of
 // arXiv:1601.00636 evaluated in fixed-width signed multiprecision arithmetic,
-// and the four inequalities of Theorem 1.1.  p, q < 2^31 and t < 2^64 keep
-// every intermediate below 2^700, well inside the 1024-bit width.
+// and the four inequalities of Theorem 1.1.  p, q < 2^32 and t < 2^70 keep
+// every intermediate below 2^720 (s^5 = t^10 < 2^700, P^5 Q^5 < 2^640), well
+// inside the 1024-bit width; larger t is reported as an overflow.
 #include "bigint.h"
 
 #include <string.h>
@@ -165,10 +166,11 @@ std::string to_decimal(Big v) {
 }  // namespace
 
 // Q_pq(t) exactly, from the factored coefficients of eq. (1.1).
-static bool q_exact(uint32_t p, uint32_t q, uint64_t t, Big &out) {
+static bool q_exact(uint32_t p, uint32_t q, uint64_t t_lo, uint64_t t_hi, Big &out) {
     Ctx c;
     const Big P = Big::from_u64((uint64_t)p * p), Q = Big::from_u64((uint64_t)q * q);
-    const Big s = c.mul(Big::from_u64(t), Big::from_u64(t));
+    const Big t = Big::from_i128(false, (u128)t_hi << 64 | t_lo);
+    const Big s = c.mul(t, t);
     const Big P2 = c.pow(P, 2), P3 = c.pow(P, 3), P4 = c.pow(P, 4), P5 = c.pow(P, 5);
     const Big Q2 = c.pow(Q, 2), Q3 = c.pow(Q, 3), Q4 = c.pow(Q, 4), Q5 = c.pow(Q, 5);
     // s^4: (2Q + P)(3Q - 2P)
@@ -198,29 +200,31 @@ static bool q_exact(uint32_t p, uint32_t q, uint64_t t, Big &out) {
     return c.ok;
 }
 
-uint32_t theorem_flags(uint32_t p, uint32_t q, uint64_t t) {
-    const u128 p2 = (u128)p * p, pq = (u128)p * q, q2 = (u128)q * q, tt = t;
+uint32_t theorem_flags(uint32_t p, uint32_t q, uint64_t t_lo, uint64_t t_hi) {
+    const u128 p2 = (u128)p * p, pq = (u128)p * q, q2 = (u128)q * q;
+    const u128 tt = (u128)t_hi << 64 | t_lo;
     uint32_t f = 0;
     if (tt > p2) f |= 1;
     if (tt > pq) f |= 2;
     if (tt > q2) f |= 4;
-    // (p^2 + t)(pq + t) > 2 t^2, both sides below 2^130: compare as Big
+    // (p^2 + t)(pq + t) > 2 t^2: both sides below 2^260 for t < 2^128, as Big
     Ctx c;
-    const Big lhs = c.mul(Big::from_i128(false, p2 + tt), Big::from_i128(false, pq + tt));
-    const Big rhs = c.scal(2, c.mul(Big::from_u64(t), Big::from_u64(t)));
+    const Big T = Big::from_i128(false, tt);
+    const Big lhs = c.mul(c.add(Big::from_i128(false, p2), T), c.add(Big::from_i128(false, pq), T));
+    const Big rhs = c.scal(2, c.mul(T, T));
     if (cmp_mag(lhs, rhs) > 0) f |= 8;
     return f;
 }
 
-bool exact_is_root(uint32_t p, uint32_t q, uint64_t t, bool *ok) {
+bool exact_is_root(uint32_t p, uint32_t q, uint64_t t_lo, uint64_t t_hi, bool *ok) {
     Big v;
-    *ok = q_exact(p, q, t, v);
+    *ok = t_hi < 64 && q_exact(p, q, t_lo, t_hi, v);
     return *ok && v.is_zero();
 }
 
-bool exact_value_decimal(uint32_t p, uint32_t q, uint64_t t, std::string *out) {
+bool exact_value_decimal(uint32_t p, uint32_t q, uint64_t t_lo, uint64_t t_hi, std::string *out) {
     Big v;
-    if (!q_exact(p, q, t, v)) return false;
+    if (t_hi >= 64 || !q_exact(p, q, t_lo, t_hi, v)) return false;
     *out = to_decimal(v);
     return true;
 }

@@ -186,13 +186,14 @@ struct RootCand {
     uint32_t pad;
     uint32_t fp[20];       // those primes
     uint32_t fe[20];       // exponents (in p^5 q^5, or p^4 / q^4 on an axis)
-    uint64_t bound;        // every positive root t is <= bound
+    uint64_t bound_lo;     // every positive root t is <= bound (128 bits:
+    uint64_t bound_hi;     // about 2^66.5 at p, q near 2^32)
     uint64_t ndiv;         // number of divisors (saturating)
 };
 struct RootHit {
     uint32_t cand;         // index of the pair
     uint32_t pad;
-    uint64_t t;
+    uint64_t t_lo, t_hi;   // the candidate t = t_hi 2^64 + t_lo
 };
 hipError_t launch_root_factor(const uint32_t *p, const uint32_t *q, uint64_t n,
                               const uint32_t *primes16, const uint32_t *magic16, uint32_t n16,

@@ -4,13 +4,16 @@
 // t^2 | p^10 q^10, i.e. t | p^5 q^5 (on the axes q = 0 or p = 0 the lowest
 // non-zero coefficient is p^8 or q^8, and t | p^4 or q^4).  A root bound on s
 // (Fujiwara's) limits the divisors tried; a candidate that vanishes modulo all
-// three primes is passed to the exact CPU check.
+// three primes is passed to the exact CPU check.  p, q < 2^32, so the bound
+// on t reaches about 2^66.5 (at p = q = 2^32 - 1): candidates are 128-bit.
 #include "devmath.h"
 #include "internal.h"
 
 namespace cuboid {
 
 namespace {
+
+typedef unsigned __int128 u128;
 
 constexpr uint64_t kMask62 = (1ull << 62) - 1;
 __constant__ uint64_t kModC[3] = {57, 87, 117};   // moduli 2^62 - c
@@ -40,13 +43,18 @@ __device__ __forceinline__ uint64_t small_mul(uint64_t a, uint32_t k, uint64_t c
     return mulmod62(a, k, c, M);
 }
 
-// Q_pq(t) mod M, coefficients as in eq. (1.1)
-__device__ uint64_t q_mod62(uint32_t p, uint32_t q, uint64_t t, uint64_t c) {
+// x mod M for any 64-bit x: x < 2^64 = 4 M + 4 c, so at most four subtractions
+__device__ __forceinline__ uint64_t red64(uint64_t x, uint64_t M) {
+    while (x >= M) x -= M;
+    return x;
+}
+
+// Q_pq(t) mod M for t = t_hi 2^64 + t_lo, coefficients as in eq. (1.1)
+__device__ uint64_t q_mod62(uint32_t p, uint32_t q, uint64_t t_lo, uint64_t t_hi, uint64_t c) {
     const uint64_t M = (1ull << 62) - c;
-    uint64_t P = (uint64_t)p * p, Q = (uint64_t)q * q;     // < 2^62
-    if (P >= M) P -= M;
-    if (Q >= M) Q -= M;
-    while (t >= M) t -= M;
+    const uint64_t P = red64((uint64_t)p * p, M), Q = red64((uint64_t)q * q, M);   // p^2 < 2^64
+    // 2^64 = 4 M + 4 c, so t = t_hi (4 c) + t_lo (mod M)
+    const uint64_t t = addmod62(mulmod62(red64(t_hi, M), 4 * c, c, M), red64(t_lo, M), M);
     const uint64_t s = mulmod62(t, t, c, M);
     const uint64_t P2 = mulmod62(P, P, c, M), Q2 = mulmod62(Q, Q, c, M);
     const uint64_t P3 = mulmod62(P2, P, c, M), Q3 = mulmod62(Q2, Q, c, M);
@@ -118,7 +126,7 @@ __global__ void root_factor_kernel(const uint32_t *pp, const uint32_t *qq, uint6
         c.nf = 0;
         c.pad = 0;
         for (int k = 0; k < 20; ++k) { c.fp[k] = 0; c.fe[k] = 0; }
-        c.bound = 0;
+        c.bound_lo = c.bound_hi = 0;
         c.ndiv = 0;
         if (c.p == 0 && c.q == 0) { out[i] = c; continue; }     // Q = t^10: no t > 0
         if (c.q == 0) add_factors(c.p, 4, primes16, magic16, n16, c);
@@ -150,7 +158,12 @@ __global__ void root_factor_kernel(const uint32_t *pp, const uint32_t *qq, uint6
         m = fmax(m, sqrt(sqrt(a1)));
         m = fmax(m, pow(a0 / 2, 0.2));
         const double tb = sqrt(2 * m) * (1.0 + 1e-9) + 2.0;
-        c.bound = tb >= 18446744073709549568.0 ? ~0ull : (uint64_t)tb;
+        // tb < 2^67: its high and low 64-bit halves (both exact in double)
+        const double two64 = 18446744073709551616.0;
+        const double hi = floor(tb / two64);
+        const double lo = tb - hi * two64;
+        c.bound_hi = (uint64_t)hi;
+        c.bound_lo = lo >= 18446744073709549568.0 ? ~0ull : (uint64_t)lo;
         out[i] = c;
     }
 }
@@ -169,28 +182,32 @@ __global__ void root_eval_kernel(const RootCand *cand, uint64_t n_cand, const ui
         }
         const RootCand &c = cand[lo];
         uint64_t k = w - prefix[lo];
-        // mixed-radix digits of k give the exponent of each prime in t
-        uint64_t t = 1;
+        const u128 bound = (u128)c.bound_hi << 64 | c.bound_lo;
+        // mixed-radix digits of k give the exponent of each prime in t; t stays
+        // at most bound < 2^68 before each step, so t * fp < 2^100 cannot wrap
+        u128 t = 1;
         bool over = false;
         for (uint32_t f = 0; f < c.nf && !over; ++f) {
             const uint64_t e1 = c.fe[f] + 1;
             uint64_t d = k % e1;
             k /= e1;
             while (d--) {
-                if (t > c.bound / c.fp[f]) { over = true; break; }
                 t *= c.fp[f];
+                if (t > bound) { over = true; break; }
             }
         }
-        if (over || t > c.bound) continue;
+        if (over) continue;
+        const uint64_t t_lo = (uint64_t)t, t_hi = (uint64_t)(t >> 64);
         bool zero = true;
-        for (int j = 0; j < 3 && zero; ++j) zero = q_mod62(c.p, c.q, t, kModC[j]) == 0;
+        for (int j = 0; j < 3 && zero; ++j) zero = q_mod62(c.p, c.q, t_lo, t_hi, kModC[j]) == 0;
         if (zero) {
             const unsigned long long pos = atomicAdd(n_hits, 1ull);
             if (pos < cap) {
                 RootHit h;
                 h.cand = (uint32_t)lo;
                 h.pad = 0;
-                h.t = t;
+                h.t_lo = t_lo;
+                h.t_hi = t_hi;
                 hits[pos] = h;
             }
         }

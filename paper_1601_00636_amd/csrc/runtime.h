@@ -191,8 +191,31 @@ struct CtxLock {
     CtxLock &operator=(const CtxLock &) = delete;
 };
 
+// A call's reference on a context, taken from the caller's handle (an opaque
+// token, see api.cpp).  While it is held, cuboid_destroy returns E_BUSY, so
+// the context outlives the call.  Empty if the handle names no live context.
+class CtxRef {
+   public:
+    explicit CtxRef(cuboid_ctx *handle);
+    ~CtxRef();
+    cuboid_ctx *get() const { return ctx_; }
+    explicit operator bool() const { return ctx_ != nullptr; }
+    CtxRef(const CtxRef &) = delete;
+    CtxRef &operator=(const CtxRef &) = delete;
+
+   private:
+    cuboid_ctx *ctx_ = nullptr;
+    uint32_t slot_ = 0;
+};
+
+// First statement of an entry point taking a context handle `h`: holds a
+// reference for the rest of the call and turns `h` into the context itself.
+#define CTX_ENTER(h)                                \
+    cuboid::CtxRef ctx_ref_(h);                     \
+    if (!ctx_ref_) return CUBOID_E_NOT_LOADED;      \
+    h = ctx_ref_.get()
+
 const char *status_text(int s);
-bool ctx_is_live(cuboid_ctx *ctx);
 bool is_prime_u32(uint32_t x);
 int canonical_primes(const uint32_t *primes, uint32_t n, std::vector<uint32_t> *sorted);
 int build_plan(cuboid_ctx *ctx, const std::vector<uint32_t> &primes, Plan **out);

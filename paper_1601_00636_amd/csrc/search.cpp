@@ -183,7 +183,7 @@ int cuboid_search_start(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_prim
                         cuboid_search **out) {
     if (!out) return CUBOID_E_ARG;
     *out = nullptr;
-    if (!ctx_is_live(ctx)) return CUBOID_E_NOT_LOADED;
+    CTX_ENTER(ctx);
     if (p < kSearchMinP) return CUBOID_E_RANGE;
     if (p > kRegionMaxP) return CUBOID_E_LIMIT;
     if (q < least_q(p) || q > 59u * p) return CUBOID_E_RANGE;

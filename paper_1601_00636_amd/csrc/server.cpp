@@ -460,7 +460,7 @@ extern "C" {
 
 int cuboid_server_start(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes,
                         const cuboid_server_config *cfg, cuboid_server **out) {
-    if (!ctx_is_live(ctx)) return CUBOID_E_NOT_LOADED;
+    CTX_ENTER(ctx);
     if (!out) return CUBOID_E_ARG;
     *out = nullptr;
     std::vector<uint32_t> sorted;

@@ -67,7 +67,7 @@ extern "C" {
 int cuboid_write_table_files(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes,
                              const char *tables_path, const char *primes_path,
                              const char *text_path) {
-    if (!ctx_is_live(ctx)) return CUBOID_E_NOT_LOADED;
+    CTX_ENTER(ctx);
     if (!tables_path || !primes_path) return CUBOID_E_ARG;
     std::vector<uint32_t> sorted;
     int st = canonical_primes(primes, n_primes, &sorted);
@@ -120,7 +120,7 @@ int cuboid_write_table_files(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n
 
 int cuboid_check_table_files(cuboid_ctx *ctx, const char *tables_path, const char *primes_path,
                              uint32_t *primes_out, uint32_t cap, uint32_t *n_primes) {
-    if (!ctx_is_live(ctx)) return CUBOID_E_NOT_LOADED;
+    CTX_ENTER(ctx);
     if (!tables_path || !primes_path || !n_primes || (cap && !primes_out)) return CUBOID_E_ARG;
     *n_primes = 0;
     std::vector<uint8_t> items, tables;

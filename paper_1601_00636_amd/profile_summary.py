@@ -6,6 +6,8 @@ usage:
   python -m paper_1601_00636_amd.profile_summary counters DB1,DB2 "COMMANDS" UNITS
 
 `trace`: per-kernel dispatch counts and durations of a --kernel-trace run.
+`counters`: SQ counters of the sweep's largest dispatches per launch and per
+64x64 unit (profiles/sweep_counters.json, keyed by the source hash as below).
 `traffic`: FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the sweep kernel's
 largest launches, scaled by what the same counters read for a device copy of
 2^30 bytes (bench.py --calibrate-copy), and writes profiles/sweep_traffic.json
@@ -98,7 +100,10 @@ def traffic(fetch_db, write_db, cfetch_db, cwrite_db, command, launches=4):
 
 
 def counters(dbs, command, units):
-    """SQ counters of the largest sweep dispatches, per dispatch and per unit."""
+    """SQ counters of the largest sweep dispatches, per dispatch and per unit;
+    also writes profiles/sweep_counters.json keyed by the sweep source's hash
+    (bench.py turns the per-unit figures into issue fractions while the
+    source is unchanged)."""
     rows = {}
     for db in dbs:
         c = sqlite3.connect(db)
@@ -106,6 +111,13 @@ def counters(dbs, command, units):
                 "select counter_name, value, duration from counters_collection where "
                 "kernel_name like '%sweep%' order by duration desc"):
             rows.setdefault(name, []).append((d, v))
+    rec = {"kernel_source_sha256": sweep_source_hash(), "units_per_launch": units,
+           "per_unit": {}}
+    for name in sorted(rows):
+        top = sorted(rows[name], reverse=True)[:2]
+        rec["per_unit"][name] = sum(x[1] for x in top) / len(top) / units
+    with open(os.path.join(ROOT, "profiles", "sweep_counters.json"), "w") as f:
+        json.dump(rec, f, indent=1)
     out = ["# SQ counters of the sweep kernel (batched 4096-rectangle workload)\n\n",
            "Commands (one counter group per run):\n\n    %s\n\n" % command.replace(";", "\n   "),
            "Averages over the 2 largest dispatches (the timed batched launches); "

@@ -3,6 +3,13 @@ import sys
 
 import pytest
 
+try:
+    # torch's HIP runtime is mapped first, so that libcuboid (loaded by the
+    # binding after torch in any case) shares it: one runtime per test process
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)

@@ -6,15 +6,25 @@ Workloads (sieve over all coprime p != q in the square, primes as listed):
   c2  1 <= p, q <= 10^4,   primes 3..97
   c3  1 <= p, q <= 10^5,   primes 3..997
   c4s a seeded sample of the batched workload's rectangles, primes 3..499
+  c4  every one of the batched workload's 4096 rectangles, primes 3..499
+      (oracle_c4.npz: per-request counts, pair counts and survivors)
+  top region (1.2) row by row, primes 11..541, at three places of the paper's
+      range (sec. 5-6): rows around 2^24, the rows where 59 p crosses 2^31,
+      and the last rows below p_max = floor(2^32 / 59) = 72796055, whose q
+      reach 4.29e9 (oracle_top.json: per-row counts, pair counts, survivors
+      and deepest first rejecter)
   s6  region (1.2) for p = 1..154000, primes 11..541 (the scan of section 6),
       per hundred of p: the deepest prime some pair was tested against
 
-usage: python tests/golden/make_golden.py [c1 c2 c3 c4s s6]
+usage: python tests/golden/make_golden.py [c1 c2 c3 c4s c4 top s6] [--threads N]
 """
 import json
 import os
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
@@ -76,6 +86,70 @@ def c4_sample():
     print("c4s", len(picks), "requests", out["oracle_seconds"], "s")
 
 
+def c4_full(threads=0):
+    from paper_1601_00636_amd.workloads import batched_requests, PRIMES_BATCHED
+    reqs = batched_requests(4096)
+    for r in PRIMES_BATCHED:
+        oracle.table(r)
+    n, k = len(reqs), len(PRIMES_BATCHED)
+    counts = np.zeros((n, k), dtype=np.uint64)
+    pairs = np.zeros(n, dtype=np.uint64)
+    nsurv = np.zeros(n, dtype=np.uint64)
+    surv = []
+    t = time.time()
+    for i, (p0, p1, q0, q1) in enumerate(reqs):
+        res = oracle.sieve(p0, p1, q0, q1, PRIMES_BATCHED, cap=1 << 16, threads=threads)
+        assert res["n_survivors"] <= 1 << 16
+        counts[i] = res["counts"]
+        pairs[i] = res["n_pairs"]
+        nsurv[i] = res["n_survivors"]
+        surv.append(np.asarray(res["survivors"], dtype=np.uint64))
+        if i % 256 == 255:
+            print("c4 %d requests: %.0f s" % (i + 1, time.time() - t), flush=True)
+    offsets = np.zeros(n + 1, dtype=np.uint64)
+    offsets[1:] = np.cumsum(nsurv)
+    np.savez_compressed(os.path.join(HERE, "oracle_c4.npz"),
+                        rects=np.array(reqs, dtype=np.uint64),
+                        primes=np.array(PRIMES_BATCHED, dtype=np.uint32),
+                        counts=counts, n_pairs=pairs, n_survivors=nsurv,
+                        survivor_offsets=offsets,
+                        survivors=np.concatenate(surv) if surv else np.zeros(0, np.uint64),
+                        oracle_seconds=np.array(time.time() - t))
+    print("c4 pairs", int(pairs.sum()), "survivors", int(nsurv.sum()),
+          "%.0f s" % (time.time() - t))
+
+
+# region rows at the top of the paper's range: around 2^24, where 59 p crosses
+# 2^31 (2^31 / 59 = 36398027.1...), and the last rows below p_max
+TOP_ROWS = (list(range(16777214, 16777218)) + list(range(36398026, 36398030))
+            + list(range(72796052, 72796056)))
+
+
+def top_rows(workers=6):
+    primes = primes_in(11, 541)
+    for r in primes:
+        oracle.table(r)
+    t = time.time()
+
+    def one(p):
+        res = oracle.sieve_region(p, p, primes, threads=1)
+        print("top row %d: %d pairs, %.0f s" % (p, res["n_pairs"], time.time() - t), flush=True)
+        return dict(p=p, qmin=oracle.region_qmin(p), qmax=59 * p,
+                    counts=[int(c) for c in res["counts"]], n_pairs=int(res["n_pairs"]),
+                    n_survivors=int(res["n_survivors"]),
+                    survivors=[list(x) for x in res["survivors"]],
+                    max_depth=int(res["max_depth"]))
+    # the longest rows first
+    order = sorted(TOP_ROWS, reverse=True)
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        rows = dict(zip(order, ex.map(one, order)))
+    out = dict(workload="top", primes=primes, rows=[rows[p] for p in TOP_ROWS],
+               oracle_seconds=round(time.time() - t, 1))
+    with open(os.path.join(HERE, "oracle_top.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print("top", len(TOP_ROWS), "rows", out["oracle_seconds"], "s")
+
+
 def section6(p_max=154000, band=100):
     primes = primes_in(11, 541)
     for r in primes:
@@ -108,10 +182,20 @@ def section6(p_max=154000, band=100):
 
 
 if __name__ == "__main__":
-    names = sys.argv[1:] or ["c1", "c2", "c3", "c4s"]
+    args = sys.argv[1:]
+    threads = 0
+    if "--threads" in args:
+        k = args.index("--threads")
+        threads = int(args[k + 1])
+        del args[k:k + 2]
+    names = args or ["c1", "c2", "c3", "c4s"]
     for nm in names:
         if nm == "c4s":
             c4_sample()
+        elif nm == "c4":
+            c4_full(threads)
+        elif nm == "top":
+            top_rows(threads or 6)
         elif nm == "s6":
             section6()
         else:

@@ -44,28 +44,37 @@ def test_canonical_primes():
 
 
 def test_exact_value_matches_python_ints():
+    # the whole coordinate range p, q < 2^32 and t up to 2^70 (the root bound
+    # of eq. 1.1 reaches about 2^66.5 there)
     rng = random.Random(17)
-    for _ in range(3000):
-        p, q = rng.randrange(0, 2**31), rng.randrange(0, 2**31)
-        t = rng.randrange(0, 2**64)
+    for k in range(3000):
+        hi = 2**31 if k % 2 else 2**32
+        p, q = rng.randrange(0, hi), rng.randrange(0, hi)
+        t = rng.randrange(0, 2**64) if k % 3 else rng.randrange(0, 2**70)
         assert cb.cuboid_exact_value(p, q, t) == poly.q_value(p, q, t)
-    for p, q, t in [(0, 0, 0), (1, 2, 0), (2**31 - 1, 2**31 - 1, 2**64 - 1), (5, 0, 25)]:
+    for p, q, t in [(0, 0, 0), (1, 2, 0), (2**31 - 1, 2**31 - 1, 2**64 - 1), (5, 0, 25),
+                    (2**32 - 1, 2**32 - 1, 2**70 - 1), (2**32 - 1, 0, 2**64), (2**32 - 1, 1, 2**67)]:
         assert cb.cuboid_exact_value(p, q, t) == poly.q_value(p, q, t)
+    with pytest.raises(cb.CuboidError) as e:
+        cb.cuboid_exact_value(3, 5, 2**70)
+    assert e.value.status == cb.E_LIMIT
 
 
 def test_exact_check_roots_and_flags():
-    for p in (1, 2, 12, 1000, 2**31 - 1):
+    for p in (1, 2, 12, 1000, 2**31 - 1, 2**31, 3000000019, 2**32 - 1):
         z, f = cb.cuboid_exact_check(p, p, p * p)
         assert z and f == poly.theorem_1_1_flags(p, p, p * p)
         assert not cb.cuboid_exact_check(p, p, p * p + 1)[0]
         z, _ = cb.cuboid_exact_check(p, 0, p * p)
         assert z
     rng = random.Random(3)
-    for _ in range(2000):
-        p, q, t = rng.randrange(0, 2**31), rng.randrange(0, 2**31), rng.randrange(0, 2**64)
+    for k in range(2000):
+        hi = 2**32 if k % 2 else 2**31
+        p, q = rng.randrange(0, hi), rng.randrange(0, hi)
+        t = rng.randrange(0, 2**64) if k % 3 else rng.randrange(0, 2**70)
         assert cb.cuboid_exact_check(p, q, t)[1] == poly.theorem_1_1_flags(p, q, t)
     with pytest.raises(cb.CuboidError) as e:
-        cb.cuboid_exact_check(2**31, 1, 5)
+        cb.cuboid_exact_check(2**31, 1, 2**70)
     assert e.value.status == cb.E_LIMIT
 
 
@@ -127,13 +136,25 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2 and "one GPU" in r.stderr
 
 
-def test_streams_of_another_runtime_are_refused():
-    class FakeTorchStream:
+def test_stream_arguments():
+    # torch and the library share one HIP runtime, so a torch stream's handle
+    # is passed as is; the default (null) stream is waited for, then the
+    # context's own stream runs the call
+    class TorchStream:
         cuda_stream = 0x1234
     class DefaultTorchStream:
         cuda_stream = 0
+        waited = False
+        def synchronize(self):
+            self.waited = True
     assert cb._stream(None) is None and cb._stream(0) is None
-    assert cb._stream(DefaultTorchStream()) is None
+    d = DefaultTorchStream()
+    assert cb._stream(d) is None and d.waited
     assert cb._stream(0x5000).value == 0x5000
-    with pytest.raises(ValueError):
-        cb._stream(FakeTorchStream())
+    assert cb._stream(TorchStream()).value == 0x1234
+
+
+def test_one_hip_runtime_after_load():
+    # torch is mapped before the library, so at most one libamdhip64 is mapped
+    cb.lib()
+    assert len(cb.hip_runtimes()) <= 1

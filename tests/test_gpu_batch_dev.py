@@ -146,3 +146,63 @@ def test_fresh_context_call_by_call_batches():
         assert [int(c) for c in out[i]["counts"]] == [int(c) for c in ref["counts"]]
         assert [int(c) for c in counts[i]] == [int(c) for c in ref["counts"]]
         assert [int(e["idx"]) for e in surv if int(e["req"]) == i] == [int(x) for x in ref["survivors"]]
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_torch_tensors_on_a_torch_stream(ctx, graphs):
+    # results written into torch device tensors (by data_ptr()) on a torch
+    # stream other than the default one, behind torch work queued on that
+    # stream, against the oracle request by request
+    import torch
+    primes = wl.PRIMES_C1
+    reqs = wl.random_rectangles(40, seed=41, max_coord=3000, max_side=200) + [(1, 200, 1, 200)]
+    n, k = len(reqs), len(primes)
+    cb.cuboid_enable_graphs(ctx, graphs)
+    side = torch.cuda.Stream()
+    try:
+        with torch.cuda.stream(side):
+            # garbage queued on the stream first: the call must come after it
+            counts = torch.full((n, k), -1, dtype=torch.int64, device="cuda")
+            pairs = torch.full((n,), -1, dtype=torch.int64, device="cuda")
+            surv = torch.full((1 << 14, 2), -1, dtype=torch.int64, device="cuda")
+            tb = cb.TensorBatch(counts, pairs, surv)
+            for rep in range(2):
+                assert cb.cuboid_sieve_batch_dev(ctx, reqs, primes, tb, stream=side) == cb.OK
+                # torch work after the call on the same stream sees the results
+                total = int(pairs.sum().item())
+                c, p, s = tb.read()
+                assert total == int(p.sum())
+                for i, rect in enumerate(reqs):
+                    ref = oracle.sieve(*rect, primes)
+                    assert int(p[i]) == ref["n_pairs"]
+                    assert [int(x) for x in c[i]] == [int(x) for x in ref["counts"]]
+                    assert [int(e["idx"]) for e in s if int(e["req"]) == i] == \
+                        [int(x) for x in ref["survivors"]]
+                counts.fill_(-1)
+                pairs.fill_(-1)
+        side.synchronize()
+    finally:
+        cb.cuboid_enable_graphs(ctx, True)
+
+
+def test_torch_default_stream(ctx):
+    import torch
+    primes = wl.PRIMES_C2
+    reqs = [(1, 3000, 1, 2000), (10**6, 10**6 + 700, 5, 900)]
+    counts = torch.zeros((2, len(primes)), dtype=torch.int64, device="cuda")
+    pairs = torch.zeros(2, dtype=torch.int64, device="cuda")
+    tb = cb.TensorBatch(counts, pairs)
+    assert cb.cuboid_sieve_batch_dev(ctx, reqs, primes, tb,
+                                     stream=torch.cuda.current_stream()) in (cb.OK, cb.E_CAPACITY)
+    c, p, _ = tb.read()
+    for i, rect in enumerate(reqs):
+        ref = oracle.sieve(*rect, primes)
+        assert int(p[i]) == ref["n_pairs"]
+        assert [int(x) for x in c[i]] == [int(x) for x in ref["counts"]]
+
+
+def test_one_hip_runtime():
+    # the library and torch share torch's HIP runtime
+    import torch  # noqa: F401
+    cb.lib()
+    assert len(cb.hip_runtimes()) == 1

@@ -158,23 +158,18 @@ def test_result_arrays_reused_across_calls(pair):
 
 
 def test_replays_on_a_caller_stream(pair):
-    # a stream of the HIP runtime the library links (the loaded libamdhip64)
-    import ctypes
-    hip = ctypes.CDLL("libamdhip64.so.7")
-    handle = ctypes.c_void_p()
-    assert hip.hipStreamCreate(ctypes.byref(handle)) == 0
-    try:
-        g, e = pair
-        primes = wl.PRIMES_C2
-        for seed in range(3):
-            rects = _batch(700 + seed, 62)
-            st_g, out_g = cb.cuboid_sieve_batch(g, rects, primes, caps=64, stream=handle.value)
-            st_e, out_e = cb.cuboid_sieve_batch(e, rects, primes, caps=64)
-            assert st_g == st_e == cb.OK
-            _same_batch(out_g, out_e)
-            # the context's own work between replays on the caller's stream
-            one = cb.cuboid_sieve_range(g, 3, 900, 7, 1100, primes)
-            assert one["n_pairs"] == cb.cuboid_sieve_range(e, 3, 900, 7, 1100, primes)["n_pairs"]
-    finally:
-        assert hip.hipStreamSynchronize(handle) == 0
-        assert hip.hipStreamDestroy(handle) == 0
+    # a torch stream: torch and the library share one HIP runtime
+    import torch
+    side = torch.cuda.Stream()
+    g, e = pair
+    primes = wl.PRIMES_C2
+    for seed in range(3):
+        rects = _batch(700 + seed, 62)
+        st_g, out_g = cb.cuboid_sieve_batch(g, rects, primes, caps=64, stream=side)
+        st_e, out_e = cb.cuboid_sieve_batch(e, rects, primes, caps=64)
+        assert st_g == st_e == cb.OK
+        _same_batch(out_g, out_e)
+        # the context's own work between replays on the caller's stream
+        one = cb.cuboid_sieve_range(g, 3, 900, 7, 1100, primes)
+        assert one["n_pairs"] == cb.cuboid_sieve_range(e, 3, 900, 7, 1100, primes)["n_pairs"]
+    side.synchronize()

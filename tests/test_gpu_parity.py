@@ -246,9 +246,6 @@ def test_error_codes(ctx):
     with pytest.raises(cb.CuboidError) as e:
         cb.cuboid_table_bytes(ctx, 12)
     assert e.value.status == cb.E_PRIMES
-    with pytest.raises(cb.CuboidError) as e:
-        cb.cuboid_root_check(ctx, [2**31], [1])
-    assert e.value.status == cb.E_LIMIT
 
 
 def test_destroyed_context_is_refused():
@@ -281,6 +278,25 @@ def test_root_check_degenerate_pairs(ctx):
     assert [tuple(x[:4]) for x in got] == [tuple(x) for x in ref]
     # p = q gives the root t = p^2 (Q_pp = -(p^2 - t)(p^2 + t)(p^4 + t^2)^4)
     assert (12, 12, 144) in [tuple(x[:3]) for x in got]
+
+
+def test_root_check_whole_u32_domain(ctx):
+    # coordinates up to 2^32 - 1, the sieve's own range (q = 59 p reaches
+    # 4.29e9 at the paper's p_max): the root bound on t passes 2^64 there, so
+    # candidates are 128-bit; roots p^2 for p = q and q = 0 (eq. 1.1)
+    rng = np.random.Generator(np.random.PCG64(11))
+    pairs = [(2**32 - 1, 2**32 - 1), (2**32 - 1, 0), (0, 2**32 - 1), (2**31, 0), (2**31, 2**31),
+             (3000000019, 3000000019), (4294967291, 4294967279), (2**32 - 1, 1), (1, 2**32 - 1),
+             (72796055, 4294967245), (36398028, 2147483652), (2**31 - 1, 2**31 + 1)]
+    p = rng.integers(2**31, 2**32, 40)
+    q = rng.integers(2**31, 2**32, 40)
+    p[:6] = q[:6]   # six more with a root
+    pairs += list(zip(p.tolist(), q.tolist()))
+    got = cb.cuboid_root_check(ctx, [a for a, _ in pairs], [b for _, b in pairs])
+    ref = oracle.root_check(pairs)
+    assert [tuple(x[:4]) for x in got] == [tuple(x) for x in ref]
+    assert (2**32 - 1, 2**32 - 1, (2**32 - 1)**2) in [tuple(x[:3]) for x in got]
+    assert len(got) >= 11   # at least the p = q and (p, 0) pairs
 
 
 def test_root_check_random_pairs(ctx):

@@ -77,3 +77,62 @@ def test_threads_on_several_contexts():
     finally:
         for c in ctxs:
             assert cb.cuboid_destroy(c) == cb.OK
+
+
+def test_destroy_while_calls_run():
+    # threads loop on one context while another thread destroys it: every
+    # call returns OK or E_NOT_LOADED (once the context is gone), destroy
+    # returns E_BUSY while a call holds the context, and nothing crashes
+    ctx = cb.cuboid_create(0)
+    primes = wl.PRIMES_C2
+    ref = cb.cuboid_sieve_range(ctx, 1, 700, 1, 900, primes)["n_pairs"]
+    seen, errs = [], []
+    started = threading.Barrier(5)
+
+    def worker():
+        started.wait()
+        for _ in range(2000):
+            try:
+                r = cb.cuboid_sieve_range(ctx, 1, 700, 1, 900, primes)
+                if r["n_pairs"] != ref:
+                    errs.append(r["n_pairs"])
+                seen.append(cb.OK)
+            except cb.CuboidError as e:
+                seen.append(e.status)
+                if e.status != cb.E_NOT_LOADED:
+                    errs.append(e)
+                return
+
+    ts = [threading.Thread(target=worker) for _ in range(4)]
+    for t in ts:
+        t.start()
+    started.wait()
+    busy = 0
+    while True:
+        st = cb.cuboid_destroy(ctx)
+        if st == cb.OK:
+            break
+        assert st == cb.E_BUSY
+        busy += 1
+    for t in ts:
+        t.join(timeout=120)
+    assert not errs, errs
+    assert set(seen) <= {cb.OK, cb.E_NOT_LOADED}
+    assert cb.cuboid_destroy(ctx) == cb.E_NOT_LOADED
+
+
+def test_stale_handle_after_a_new_context():
+    # a destroyed context's handle stays refused when a new context takes
+    # its place (handles carry a generation, not an address)
+    old = cb.cuboid_create(0)
+    assert cb.cuboid_destroy(old) == cb.OK
+    new = cb.cuboid_create(0)
+    try:
+        assert new.value != old.value
+        with pytest.raises(cb.CuboidError) as e:
+            cb.cuboid_sieve_range(old, 1, 5, 1, 5, [11])
+        assert e.value.status == cb.E_NOT_LOADED
+        assert cb.cuboid_destroy(old) == cb.E_NOT_LOADED
+        assert cb.cuboid_sieve_range(new, 1, 200, 1, 200, wl.PRIMES_C1)["n_survivors"] == 26
+    finally:
+        assert cb.cuboid_destroy(new) == cb.OK
