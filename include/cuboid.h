@@ -282,6 +282,35 @@ int cuboid_sieve_batch_dev(cuboid_ctx *ctx, const cuboid_request *req, uint32_t 
                            uint64_t *n_survivors, void *hip_stream);
 
 /*
+ * cuboid_sieve_batch_dev for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, results and errors, but the call allocates no
+ * device or pinned memory.  Its device scratch (descriptors, row order,
+ * counter replicas, survivor list and sort buffer, the survivor count) is
+ * one fixed array of 64 MiB per GPU inside the library, held until the
+ * process ends; every call on a GPU shares it, and the library makes those
+ * calls take turns (each holds the array until its work has completed), so
+ * they never overlap on it.  Every counter it needs is cleared by each call.
+ * Requirements and limits:
+ *   - the prime list's tables and the resident row table up to the largest
+ *     p1 must exist: any earlier sieve call on this context with the same
+ *     prime list and rows at least as far builds them (a one-pair
+ *     cuboid_sieve_range at (p1, 1) does); otherwise E_NOT_LOADED;
+ *   - p1 <= 2^24 (E_LIMIT beyond), launched call by call (no graph);
+ *   - E_LIMIT when the requests' descriptors and one set of counters do not
+ *     fit the array with room for 1024 survivors (about 75 000 requests at
+ *     94 primes), or when more survivors arise than the array holds (up to
+ *     2^19; counts and pairs are complete, the list unspecified).
+ * Rows of the largest requests keep their natural order once 6.3 million
+ * regrouped rows fill the array's row-order part (results are unchanged).
+ */
+int cuboid_sieve_batch_dev_noalloc(cuboid_ctx *ctx, const cuboid_request *req, uint32_t n_req,
+                                   const uint32_t *primes, uint32_t n_primes,
+                                   uint64_t *counts_dev, uint64_t *pairs_dev,
+                                   void *survivors_dev, uint64_t surv_cap,
+                                   uint64_t *n_survivors, void *hip_stream);
+
+/*
  * Device memory on the context's GPU for the _dev entry points, and a
  * synchronous copy back to host memory (on hip_stream, NULL = the context's
  * stream).  cuboid_device_free waits for the context's stream first; NULL is a

@@ -134,6 +134,8 @@ def _load():
         "cuboid_sieve_batch": ([vp, P(cuboid_request), u32, P(u32), u32, P(cuboid_result), vp], i32),
         "cuboid_sieve_batch_dev": ([vp, P(cuboid_request), u32, P(u32), u32, vp, vp, vp, u64,
                                     P(u64), vp], i32),
+        "cuboid_sieve_batch_dev_noalloc": ([vp, P(cuboid_request), u32, P(u32), u32, vp, vp, vp,
+                                            u64, P(u64), vp], i32),
         "cuboid_device_alloc": ([vp, ctypes.c_size_t, P(vp)], i32),
         "cuboid_probe_peaks": ([vp, P(ctypes.c_double), P(ctypes.c_double)], i32),
         "cuboid_device_free": ([vp, vp], i32),
@@ -536,6 +538,28 @@ def cuboid_sieve_batch_dev(ctx, requests, primes, dev, stream=None):
     dev.n_survivors = int(ns.value)
     if st not in (OK, E_CAPACITY, E_LIMIT):
         _check(st, "cuboid_sieve_batch_dev")
+    return st
+
+
+def cuboid_sieve_batch_dev_noalloc(ctx, requests, primes, dev, stream=None):
+    """cuboid_sieve_batch_dev without any device allocation: scratch comes from
+    the library's fixed per-GPU array; the prime list's tables and rows up to
+    the largest p must be resident from an earlier call.  Same arguments and
+    results as cuboid_sieve_batch_dev."""
+    pr = _arr(primes, np.uint32)
+    reqa = np.ascontiguousarray(np.asarray(requests, dtype=np.uint32).reshape(-1, 4))
+    n = reqa.shape[0]
+    if n != dev.n_req or len(pr) != dev.n_primes:
+        raise ValueError("device buffers are for %d requests x %d primes" % (dev.n_req, dev.n_primes))
+    ns = ctypes.c_uint64(0)
+    st = _load().cuboid_sieve_batch_dev_noalloc(
+        ctx, reqa.ctypes.data_as(P(cuboid_request)), n, _p(pr, u32), len(pr),
+        ctypes.c_void_p(dev.counts), ctypes.c_void_p(dev.pairs),
+        ctypes.c_void_p(dev.surv) if dev.surv else None, dev.surv_cap, ctypes.byref(ns),
+        _stream(stream))
+    dev.n_survivors = int(ns.value)
+    if st not in (OK, E_CAPACITY, E_LIMIT):
+        _check(st, "cuboid_sieve_batch_dev_noalloc")
     return st
 
 

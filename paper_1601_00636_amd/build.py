@@ -19,6 +19,7 @@ SOURCES = [
     "kernels_sieve.hip",
     "kernels_roots.hip",
     "kernels_peaks.hip",
+    "noalloc.hip",
     "bigint.cpp",
     "graph.cpp",
     "region.cpp",

@@ -118,6 +118,7 @@ int init_ctx(cuboid_ctx *ctx, int dev) {
     HIPCHK(launch_wheel((uint64_t *)ctx->wheel.p, ctx->stream));
     HIPCHK(ctx->patterns.ensure(kPatBytes));
     HIPCHK(launch_patterns((uint64_t *)ctx->patterns.p, ctx->stream));
+    HIPCHK(noalloc_scratch_setup(dev));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return CUBOID_OK;
 }

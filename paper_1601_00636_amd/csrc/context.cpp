@@ -295,7 +295,8 @@ cuboid_tuning tuning_for(cuboid_ctx *ctx, const std::vector<uint32_t> &primes, c
 // Unit space of one launch: each request's first unit and unit count, and
 // which requests get their rows regrouped by factor count (prefix sums of
 // regrouped rows and of 8192-row chunks).  Counter slots are the caller's.
-void shape_reqs(cuboid_ctx *ctx, std::vector<ReqDesc> &reqs, LaunchShape *sh) {
+void shape_reqs(cuboid_ctx *ctx, std::vector<ReqDesc> &reqs, LaunchShape *sh,
+                uint64_t max_order_rows) {
     const uint32_t n = (uint32_t)reqs.size();
     sh->row_prefix.assign(n + 1, 0);
     sh->chunk_prefix.assign(n + 1, 0);
@@ -313,7 +314,7 @@ void shape_reqs(cuboid_ctx *ctx, std::vector<ReqDesc> &reqs, LaunchShape *sh) {
         max_p = std::max(max_p, r.p1);
         // band-split region requests keep their rows in natural order
         const bool group = ctx->bucketing && !(r.flags & kReqBandSplit) &&
-                           rows >= kBucketMinRows && sh->row_prefix[i] + rows <= kMaxOrderRows;
+                           rows >= kBucketMinRows && sh->row_prefix[i] + rows <= max_order_rows;
         sh->row_prefix[i + 1] = sh->row_prefix[i] + (group ? rows : 0);
         sh->chunk_prefix[i + 1] =
             sh->chunk_prefix[i] + (group ? (rows + kBucketChunk - 1) / kBucketChunk : 0);

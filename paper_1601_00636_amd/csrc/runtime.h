@@ -226,7 +226,10 @@ int ensure_rows_serving(cuboid_ctx *ctx, uint32_t p_max);   // by a drained serv
 std::vector<int32_t> count_columns(const Plan &pl, const std::vector<uint32_t> &caller);
 cuboid_tuning tuning_for(cuboid_ctx *ctx, const std::vector<uint32_t> &primes, const Plan &pl);
 int rect_valid(uint32_t p0, uint32_t p1, uint32_t q0, uint32_t q1);
-void shape_reqs(cuboid_ctx *ctx, std::vector<ReqDesc> &reqs, LaunchShape *sh);
+// max_order_rows: most rows regrouped by factor count in the launch (requests
+// past it keep their natural row order)
+void shape_reqs(cuboid_ctx *ctx, std::vector<ReqDesc> &reqs, LaunchShape *sh,
+                uint64_t max_order_rows = kMaxOrderRows);
 int sieve_core(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid_tuning &tun,
                std::vector<ReqDesc> &reqs, uint32_t n_slots, const std::vector<int32_t> *col,
                uint64_t surv_cap, hipStream_t s, CoreOut *out, const DevOut *dev = nullptr);
@@ -245,6 +248,9 @@ int run_batch_graph(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const c
                     const std::vector<int32_t> *col, uint64_t surv_cap, hipStream_t s,
                     uint64_t *units_out, const DevOut *dev = nullptr);
 void drop_graphs(cuboid_ctx *ctx);
+// the allocation-free path's device scratch (noalloc.hip): looked up once per
+// device at context creation
+hipError_t noalloc_scratch_setup(int device);
 int sieve_rects(cuboid_ctx *ctx, const std::vector<uint32_t> &caller_primes,
                 const cuboid_request *rects, uint32_t n_req, uint64_t surv_cap_total,
                 hipStream_t s, SieveOut *out, const DevOut *dev = nullptr);
