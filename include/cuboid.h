@@ -339,7 +339,12 @@ int cuboid_device_read(cuboid_ctx *ctx, void *dst, const void *src_dev, size_t b
  * takes at most `max_launch_units` 64 x 64 units from the requests admitted
  * to its stream (a large request spans several launches), so small requests
  * are not held behind large ones.  Each request's results are bit-exact those
- * of cuboid_sieve_range alone.
+ * of cuboid_sieve_range alone.  Survivors of a launch go to a device pool per
+ * stream (2^16 entries at first); a launch that overflows it is swept again
+ * with the pool grown to hold them all (up to 2^26), so survivor lists are
+ * complete.  Rows beyond the resident row table (p above 2^24, up to
+ * 2^32 - 1) get their factor lists computed per request into the device
+ * arena.
  */
 typedef struct cuboid_server cuboid_server;
 
@@ -353,8 +358,8 @@ typedef struct cuboid_server_config {
 
 typedef struct cuboid_server_stats {
     uint64_t submitted, completed, launches, units;
-    uint32_t max_admitted;        /* most requests admitted at the same time */
-    uint32_t reserved;
+    uint32_t max_admitted;        /* most requests admitted at the same time        */
+    uint32_t resweeps;            /* launches swept again after a survivor overflow */
 } cuboid_server_stats;
 
 typedef struct cuboid_request_timing {
@@ -370,8 +375,11 @@ int cuboid_server_start(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_prim
                         const cuboid_server_config *cfg, cuboid_server **out);
 
 /*
- * Queue one rectangle; *ticket identifies it.  Returns at once.
- * Errors: E_RANGE (invalid rectangle), E_LIMIT (p1 >= 2^24), E_BUSY (stopping).
+ * Queue one rectangle; *ticket identifies it.  Returns at once.  A request
+ * whose own row table (33 bytes per row, for p1 above 2^24) exceeds the
+ * whole arena, or one of whose launches leaves more than 2^26 survivors,
+ * finishes with status E_LIMIT (counts and pairs still exact in the second
+ * case).  Errors: E_RANGE (invalid rectangle), E_BUSY (stopping).
  */
 int cuboid_server_submit(cuboid_server *srv, const cuboid_request *req, uint64_t *ticket);
 

@@ -68,7 +68,7 @@ class cuboid_server_config(ctypes.Structure):
 
 class cuboid_server_stats(ctypes.Structure):
     _fields_ = [("submitted", u64), ("completed", u64), ("launches", u64), ("units", u64),
-                ("max_admitted", u32), ("reserved", u32)]
+                ("max_admitted", u32), ("resweeps", u32)]
 
 
 class cuboid_request_timing(ctypes.Structure):
@@ -702,7 +702,7 @@ def cuboid_server_stats_get(srv):
     st = cuboid_server_stats()
     _check(_load().cuboid_server_stats_get(srv, ctypes.byref(st)), "cuboid_server_stats_get")
     return dict(submitted=st.submitted, completed=st.completed, launches=st.launches,
-                units=st.units, max_admitted=st.max_admitted)
+                units=st.units, max_admitted=st.max_admitted, resweeps=st.resweeps)
 
 
 def cuboid_server_stop(srv):

@@ -11,6 +11,11 @@
 // and records an event.  The worker polls events, hands results to tickets,
 // admits pending requests as slots and arena space free up, and refills idle
 // streams, so requests arriving while others run join the next launch.
+// A launch whose survivors overflow its stream's survivor pool is swept again
+// (same units, counters into a discarded buffer) with the pool grown to hold
+// them all, so every request still gets its complete list.  Requests with
+// rows beyond the resident row table (p above 2^24) get their rows' factor
+// lists computed into the arena at their first launch.
 #include <string.h>
 #include <sys/prctl.h>
 
@@ -80,6 +85,8 @@ struct SrvReq {
     int stream = -1;
     bool has_order = false;
     uint64_t order_off = 0, order_bytes = 0;
+    bool own_rows = false;            // rows beyond the resident table:
+    uint64_t rows_off = 0, rows_bytes = 0;   // RowInfo[rows] then nfac[rows] in the arena
     std::vector<SurvEntry> surv;
     std::vector<uint64_t> counts;     // caller order, when done
     uint64_t n_pairs = 0;
@@ -88,7 +95,7 @@ struct SrvReq {
     uint64_t t_submit = 0, t_admit = 0, t_done = 0;
 };
 
-constexpr uint64_t kSurvPool = 1u << 16;      // survivors per launch held on the device
+constexpr uint64_t kSurvPool = 1u << 16;      // survivors per launch held on the device, at first
 constexpr uint64_t kSurvCopy = 1024;          // copied back with every launch
 
 struct StreamState {
@@ -100,7 +107,19 @@ struct StreamState {
     std::vector<uint64_t> launch_tickets, final_tickets;
     DevBuf reqbuf, aux, out_dev, surv, surv_n;
     HostBuf stage, out_host;
+    uint64_t surv_cap = kSurvPool;            // entries of surv (grows on overflow)
+    // the last launch's descriptors (in reqbuf), for a survivor re-sweep
+    uint32_t last_n = 0;
+    uint64_t last_units = 0;
+    size_t last_desc_off = 0;
+    uint32_t last_max_p = 0;
 };
+
+// bytes of a request's own row table: RowInfo per row, then one factor count
+// byte per row
+uint64_t own_rows_bytes(uint64_t rows) {
+    return ((rows * sizeof(RowInfo) + 255) & ~255ull) + rows;
+}
 
 }  // namespace
 
@@ -119,6 +138,7 @@ struct cuboid_server {
     std::vector<uint32_t> free_slots;
     std::vector<uint64_t> slot_owner;
     std::vector<std::unique_ptr<StreamState>> streams;
+    DevBuf discard_counts, discard_pairs;     // counters of survivor re-sweeps
     std::mutex mu;
     std::condition_variable cv_done, cv_work;
     std::deque<uint64_t> pending;
@@ -153,7 +173,19 @@ void admit(cuboid_server *S) {
         const uint64_t t = S->pending.front();
         SrvReq &r = S->reqs[t];
         if (S->free_slots.empty()) return;
-        if (r.rect.p1 > ctx->rows_R) {
+        const uint64_t rows = (uint64_t)r.rect.p1 - r.rect.p0 + 1;
+        r.own_rows = r.rect.p1 > kResidentRowsMax;
+        if (r.own_rows) {
+            r.rows_bytes = own_rows_bytes(rows);
+            if (r.rows_bytes > S->cfg.hbm_budget_bytes) {
+                // its row table alone is larger than the whole arena
+                r.status = CUBOID_E_LIMIT; r.done = true; r.t_done = now_ns();
+                r.counts.assign(S->caller.size(), 0);
+                S->pending.pop_front();
+                S->cv_done.notify_all();
+                continue;
+            }
+        } else if (r.rect.p1 > ctx->rows_R) {
             // grow the resident row table only while nothing is in flight
             if (!all_idle(S)) return;
             int st;
@@ -169,7 +201,7 @@ void admit(cuboid_server *S) {
                 continue;
             }
         }
-        const uint64_t rows = (uint64_t)r.rect.p1 - r.rect.p0 + 1;
+        if (r.own_rows && !S->arena.alloc(r.rows_bytes, &r.rows_off)) return;
         r.has_order = rows >= kBucketMinRows;
         if (r.has_order) {
             r.order_bytes = rows * 4;
@@ -178,6 +210,7 @@ void admit(cuboid_server *S) {
                     // larger than the whole arena: run it in row order
                     r.has_order = false;
                 } else {
+                    if (r.own_rows) S->arena.release(r.rows_off, r.rows_bytes);
                     return;
                 }
             }
@@ -196,6 +229,45 @@ void admit(cuboid_server *S) {
         ++S->admitted;
         S->stats.max_admitted = std::max(S->stats.max_admitted, S->admitted);
     }
+}
+
+// The sweep of the stream's last launch (its descriptors in st.reqbuf) with
+// counters into cnt/prs (n_rep replicas) and survivors into st.surv.
+hipError_t sweep_last(cuboid_server *S, StreamState &st, unsigned long long *cnt,
+                      unsigned long long *prs, uint32_t n_rep) {
+    cuboid_ctx *ctx = S->ctx;
+    SweepParams P;
+    memset(&P, 0, sizeof(P));
+    const DenseSet &ds = *S->ds;
+    P.K = ds.K;
+    for (uint32_t k = 0; k < ds.K; ++k) {
+        P.dr[k] = ds.dr[k]; P.dm[k] = ds.dm[k]; P.dinv[k] = ds.dinv[k]; P.doff[k] = ds.doff[k];
+        P.dext[k] = ds.dext[k];
+    }
+    P.dense_words = ds.words;
+    P.dense_tab = (const uint64_t *)ds.tab.p;
+    P.wheel = (const uint64_t *)ctx->wheel.p;
+    P.patterns = (const uint64_t *)ctx->patterns.p;
+    P.n_deep = ds.n_deep;
+    P.nc = S->nc;
+    P.deep = (const DeepPrime *)ds.deep.p;
+    P.vpool = (const uint8_t *)S->pl->vpool.p;
+    P.ipool = (const uint16_t *)S->pl->ipool.p;
+    P.req = (const ReqDesc *)((unsigned char *)st.reqbuf.p + st.last_desc_off);
+    P.n_req = st.last_n;
+    P.n_units = st.last_units;
+    P.counts = cnt;
+    P.pairs = prs;
+    P.n_rep = n_rep;
+    P.rep_stride_counts = (uint64_t)S->cfg.max_slots * S->nc;
+    P.rep_stride_pairs = S->cfg.max_slots;
+    P.surv = (SurvEntry *)st.surv.p;
+    P.surv_cap = st.surv_cap;
+    P.surv_n = (unsigned long long *)st.surv_n.p;
+    P.claim = (unsigned long long *)st.surv_n.p + 1;
+    P.schedule = S->tun.schedule;
+    const size_t lds = (size_t)ds.words * 8 + kSweepFixedLds;
+    return launch_sweep(P, (int)S->tun.workgroups, lds, st.last_max_p, st.s);
 }
 
 // Builds and enqueues one launch on an idle stream.
@@ -222,12 +294,27 @@ int launch(cuboid_server *S, StreamState &st) {
         d.ulo = r.units_issued;
         d.ucount = take;
         d.slot = r.slot;
-        d.rows = (const RowInfo *)ctx->rows.p;
-        d.nfac = (const uint8_t *)ctx->nfac.p;
-        d.rows_p0 = 1;
+        if (r.own_rows) {
+            uint8_t *base = (uint8_t *)S->arena_buf.p + r.rows_off;
+            const uint64_t rows = (uint64_t)r.rect.p1 - r.rect.p0 + 1;
+            d.rows = (const RowInfo *)base;
+            d.nfac = base + ((rows * sizeof(RowInfo) + 255) & ~255ull);
+            d.rows_p0 = r.rect.p0;
+        } else {
+            d.rows = (const RowInfo *)ctx->rows.p;
+            d.nfac = (const uint8_t *)ctx->nfac.p;
+            d.rows_p0 = 1;
+        }
         d.ip0 = r.rect.p0;
         d.order = r.has_order ? (const uint32_t *)((uint8_t *)S->arena_buf.p + r.order_off) : nullptr;
         if (r.units_issued == 0) {
+            if (r.own_rows) {
+                // the request's row factor lists, before its rows are regrouped
+                SRVCHK(launch_row_info((const uint32_t *)ctx->primes16.p,
+                                       (const uint32_t *)ctx->magic16.p, ctx->n16, r.rect.p0,
+                                       (uint64_t)r.rect.p1 - r.rect.p0 + 1, (RowInfo *)d.rows,
+                                       (uint8_t *)d.nfac, st.s));
+            }
             new_slots.push_back(r.slot);
             if (r.has_order) {
                 bdescs.push_back(d);
@@ -283,40 +370,13 @@ int launch(cuboid_server *S, StreamState &st) {
                                   chunk_pre.back(), (const uint64_t *)(dv + o_rpre),
                                   (uint32_t *)S->arena_buf.p, st.s));
     SRVCHK(launch_fill_u64((uint64_t *)st.surv_n.p, 2, 0, st.s));
-    SweepParams P;
-    memset(&P, 0, sizeof(P));
-    const DenseSet &ds = *S->ds;
-    P.K = ds.K;
-    for (uint32_t k = 0; k < ds.K; ++k) {
-        P.dr[k] = ds.dr[k]; P.dm[k] = ds.dm[k]; P.dinv[k] = ds.dinv[k]; P.doff[k] = ds.doff[k];
-        P.dext[k] = ds.dext[k];
-    }
-    P.dense_words = ds.words;
-    P.dense_tab = (const uint64_t *)ds.tab.p;
-    P.wheel = (const uint64_t *)ctx->wheel.p;
-    P.patterns = (const uint64_t *)ctx->patterns.p;
-    P.n_deep = ds.n_deep;
-    P.nc = S->nc;
-    P.deep = (const DeepPrime *)ds.deep.p;
-    P.vpool = (const uint8_t *)S->pl->vpool.p;
-    P.ipool = (const uint16_t *)S->pl->ipool.p;
-    P.req = (const ReqDesc *)(dv + o_desc);
-    P.n_req = n;
-    P.n_units = unit0;
-    P.counts = cnt;
-    P.pairs = prs;
-    P.n_rep = S->n_rep;
-    P.rep_stride_counts = stride_c;
-    P.rep_stride_pairs = stride_p;
-    P.surv = (SurvEntry *)st.surv.p;
-    P.surv_cap = kSurvPool;
-    P.surv_n = (unsigned long long *)st.surv_n.p;
-    P.claim = (unsigned long long *)st.surv_n.p + 1;
-    P.schedule = S->tun.schedule;
     uint32_t max_p = 0;
     for (const auto &d : descs) max_p = std::max(max_p, d.p1);
-    const size_t lds = (size_t)ds.words * 8 + kSweepFixedLds;
-    SRVCHK(launch_sweep(P, (int)S->tun.workgroups, lds, max_p, st.s));
+    st.last_n = n;
+    st.last_units = unit0;
+    st.last_desc_off = o_desc;
+    st.last_max_p = max_p;
+    SRVCHK(sweep_last(S, st, cnt, prs, S->n_rep));
     // outputs: [final][nc + 1] sums, survivor count, first survivors
     const size_t fout = final_slots.size() * (S->nc + 1) * 8;
     SRVCHK(st.out_dev.ensure(fout + 8));
@@ -362,17 +422,36 @@ int complete(cuboid_server *S, StreamState &st) {
     uint64_t nsurv = 0;
     memcpy(&nsurv, oh + fout, 8);
     st.busy = false;
+    if (nsurv > st.surv_cap && nsurv <= kMaxSurvScratch) {
+        // the pool overflowed: sweep the same units again into a pool that
+        // holds them all; the counters of the repeat go to a buffer that is
+        // never read (the launch's own counts are complete already)
+        uint64_t cap = st.surv_cap;
+        while (cap < nsurv) cap *= 2;
+        SRVCHK(st.surv.ensure(cap * sizeof(SurvEntry)));
+        st.surv_cap = cap;
+        SRVCHK(S->discard_counts.ensure((size_t)S->cfg.max_slots * S->nc * 8 + 8));
+        SRVCHK(S->discard_pairs.ensure((size_t)S->cfg.max_slots * 8 + 8));
+        SRVCHK(launch_fill_u64((uint64_t *)st.surv_n.p, 2, 0, st.s));
+        SRVCHK(sweep_last(S, st, (unsigned long long *)S->discard_counts.p,
+                          (unsigned long long *)S->discard_pairs.p, 1));
+        uint64_t again = 0;
+        SRVCHK(hipMemcpyAsync(&again, st.surv_n.p, 8, hipMemcpyDeviceToHost, st.s));
+        SRVCHK(hipStreamSynchronize(st.s));
+        if (again != nsurv) return CUBOID_E_DEVICE;
+        S->stats.resweeps++;
+    }
     if (nsurv) {
-        std::vector<SurvEntry> e(std::min<uint64_t>(nsurv, kSurvPool));
-        if (e.size() <= kSurvCopy) {
+        std::vector<SurvEntry> e(std::min<uint64_t>(nsurv, st.surv_cap));
+        if (e.size() <= kSurvCopy && nsurv <= kSurvPool) {
             memcpy(e.data(), oh + fout + 8, e.size() * sizeof(SurvEntry));
         } else {
             SRVCHK(hipMemcpyAsync(e.data(), st.surv.p, e.size() * sizeof(SurvEntry),
                                   hipMemcpyDeviceToHost, st.s));
             SRVCHK(hipStreamSynchronize(st.s));
         }
-        if (nsurv > kSurvPool) {
-            // survivors of this launch were lost: its requests cannot be listed
+        if (nsurv > st.surv_cap) {
+            // more than the largest pool: this launch's requests cannot be listed
             for (uint64_t t : st.launch_tickets) S->reqs[t].status = CUBOID_E_LIMIT;
         }
         for (const SurvEntry &x : e) S->reqs[S->slot_owner[x.req]].surv.push_back(x);
@@ -391,6 +470,7 @@ int complete(cuboid_server *S, StreamState &st) {
         r.t_done = now_ns();
         S->free_slots.push_back(r.slot);
         if (r.has_order) S->arena.release(r.order_off, r.order_bytes);
+        if (r.own_rows) S->arena.release(r.rows_off, r.rows_bytes);
         --S->admitted;
         S->stats.completed++;
     }
@@ -524,7 +604,6 @@ int cuboid_server_submit(cuboid_server *S, const cuboid_request *req, uint64_t *
     if (!S || !req || !ticket) return CUBOID_E_ARG;
     const int st = rect_valid(req->p0, req->p1, req->q0, req->q1);
     if (st) return st;
-    if (req->p1 > kResidentRowsMax) return CUBOID_E_LIMIT;
     std::lock_guard<std::mutex> g(S->mu);
     if (S->stopping) return CUBOID_E_BUSY;
     const uint64_t t = S->next_ticket++;

@@ -125,9 +125,6 @@ def test_capacity_retry_and_errors(ctx):
         with pytest.raises(cb.CuboidError) as e:
             cb.cuboid_server_submit(srv, (5, 4, 1, 1))
         assert e.value.status == cb.E_RANGE
-        with pytest.raises(cb.CuboidError) as e:
-            cb.cuboid_server_submit(srv, (1, 1 << 25, 1, 1))
-        assert e.value.status == cb.E_LIMIT
         assert cb.cuboid_destroy(ctx) == cb.E_BUSY            # a server is running
         t2 = cb.cuboid_server_submit(srv, (3, 300, 7, 500))
         assert cb.cuboid_server_poll(srv, t2, len(wl.PRIMES_C1), wait=True) is not None
@@ -153,3 +150,59 @@ def test_poisson_replay_small(ctx):
                                                            np.percentile(lat, 99)))
     for (_, rect), r in list(zip(stream, res))[::25]:
         _same(r, cb.cuboid_sieve_range(ctx, *rect, PRIMES, cap=4096))
+
+
+def test_survivor_pool_overflow_is_swept_again(ctx):
+    # with the prime 11 alone about a third of the pairs survive: requests of
+    # ~2e5 survivors each overflow the 2^16-entry pool of a launch, which is
+    # then swept again with a larger pool; every list is complete, counts
+    # are counted once
+    primes = [11]
+    rects = [(1, 1000, 1, 1000), (5000, 5600, 20000, 20900), (1, 40, 1, 40),
+             (70000, 70700, 3, 800)]
+    srv = cb.cuboid_server_start(ctx, primes, streams=2, max_launch_units=1 << 9)
+    try:
+        ts = [cb.cuboid_server_submit(srv, r) for r in rects]
+        got = [cb.cuboid_server_poll(srv, t, 1, cap=1 << 20) for t in ts]
+        stats = cb.cuboid_server_stats_get(srv)
+    finally:
+        cb.cuboid_server_stop(srv)
+    assert stats["resweeps"] > 0
+    for rect, g in zip(rects, got):
+        assert g["status"] == cb.OK
+        ref = oracle.sieve(*rect, primes, cap=1 << 20)
+        _same(g, ref)
+    assert max(g["n_survivors"] for g in got) > 1 << 16
+
+
+def test_rows_beyond_the_resident_table(ctx):
+    # p above 2^24 up to 2^32 - 1: each request's rows are factored into the
+    # arena at its first launch; against the oracle
+    primes = wl.PRIMES_C1
+    rects = [(2**31, 2**31 + 300, 5, 900), (2**32 - 200, 2**32 - 1, 1, 500),
+             (16777200, 16777300, 1, 700), (3000000019, 3000000019, 2999999000, 3000001000),
+             (1, 200, 1, 200)]
+    srv = cb.cuboid_server_start(ctx, primes, streams=2, max_launch_units=1 << 8)
+    try:
+        ts = [cb.cuboid_server_submit(srv, r) for r in rects]
+        got = [cb.cuboid_server_poll(srv, t, len(primes), cap=1 << 16) for t in ts]
+    finally:
+        cb.cuboid_server_stop(srv)
+    for rect, g in zip(rects, got):
+        assert g["status"] == cb.OK
+        _same(g, oracle.sieve(*rect, primes, cap=1 << 16))
+
+
+def test_row_table_larger_than_the_arena(ctx):
+    # a request whose own row table cannot fit the arena finishes with E_LIMIT
+    srv = cb.cuboid_server_start(ctx, wl.PRIMES_C1, hbm_budget_bytes=1 << 16)
+    try:
+        t = cb.cuboid_server_submit(srv, (2**31, 2**31 + 10000, 1, 10))
+        with pytest.raises(cb.CuboidError) as e:
+            cb.cuboid_server_poll(srv, t, len(wl.PRIMES_C1))
+        assert e.value.status == cb.E_LIMIT
+        t2 = cb.cuboid_server_submit(srv, (2**31, 2**31 + 100, 1, 300))
+        g = cb.cuboid_server_poll(srv, t2, len(wl.PRIMES_C1))
+    finally:
+        cb.cuboid_server_stop(srv)
+    _same(g, oracle.sieve(2**31, 2**31 + 100, 1, 300, wl.PRIMES_C1))
