@@ -255,6 +255,61 @@ def run_served(cb, wl, ctx, primes, seconds):
             "max_admitted": stats["max_admitted"]}
 
 
+def run_served_vs_plain(cb, wl, ctx, primes, rates=(2000, 20000, 200000), n_req=3000):
+    """The same seeded Poisson streams (areas log-uniform in [1e3, 1e9]) at
+    several offered rates, once through the server (continuous batching) and
+    once as one plain cuboid_sieve_range call per request from one thread in
+    arrival order; latency = completion - arrival (for the server: completion
+    - submission, stamped by the server)."""
+    out = {}
+    for rate in list(rates) + ["burst"]:
+        r = 1e9 if rate == "burst" else float(rate)
+        stream = wl.served_stream(rate=r, duration=1e9, max_requests=n_req)
+        if rate == "burst":
+            stream = [(0.0, rect) for _, rect in stream]
+        # served
+        srv = cb.cuboid_server_start(ctx, primes)
+        try:
+            t0 = time.perf_counter()
+            tickets = []
+            for at, rect in stream:
+                while time.perf_counter() - t0 < at:
+                    pass
+                tickets.append(cb.cuboid_server_submit(srv, rect))
+            t_sub = time.perf_counter() - t0
+            res = [cb.cuboid_server_poll(srv, t, len(primes), cap=1 << 14) for t in tickets]
+            stats = cb.cuboid_server_stats_get(srv)
+        finally:
+            cb.cuboid_server_stop(srv)
+        lat = np.array([x["latency_ns"] for x in res], dtype=np.float64) / 1e6
+        pairs = sum(x["n_pairs"] for x in res)
+        span = (max(x["done_ns"] for x in res) - min(x["submit_ns"] for x in res)) / 1e9
+        served = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                  "pairs_per_s": pairs / span, "span_s": span,
+                  "submitted_per_s": len(res) / t_sub if t_sub > 0 else None,
+                  "launches": stats["launches"], "max_admitted": stats["max_admitted"]}
+        # plain, one call per request in arrival order
+        lat_p = []
+        pairs_p = 0
+        t0 = time.perf_counter()
+        for (at, rect), x in zip(stream, res):
+            while time.perf_counter() - t0 < at:
+                pass
+            g = cb.cuboid_sieve_range(ctx, *rect, primes, cap=1 << 14)
+            lat_p.append(time.perf_counter() - t0 - at)
+            pairs_p += g["n_pairs"]
+            if g["n_pairs"] != x["n_pairs"]:
+                raise RuntimeError("served and plain results differ")
+        span_p = time.perf_counter() - t0
+        lat_p = np.array(lat_p) * 1e3
+        plain = {"p50_ms": float(np.percentile(lat_p, 50)), "p99_ms": float(np.percentile(lat_p, 99)),
+                 "pairs_per_s": pairs_p / span_p, "span_s": span_p}
+        out[str(rate)] = {"requests": len(res), "coprime_pairs": pairs, "served": served,
+                          "plain": plain,
+                          "served_over_plain_throughput": served["pairs_per_s"] / plain["pairs_per_s"]}
+    return out
+
+
 def section6_scan(cb, wl, ctx, stream, torch):
     """The scan of the paper's section 6: region (1.2), p = 1..154000, the 96
     primes 11..541, the deepest prime used reported per hundred of p."""
@@ -550,6 +605,7 @@ def main():
 
     if not args.no_extras and args.served_seconds > 0:
         res["extras"]["served"] = run_served(cb, wl, ctx, primes, args.served_seconds)
+        res["extras"]["served_vs_plain"] = run_served_vs_plain(cb, wl, ctx, primes)
 
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = run_cpu_baseline(reqs, primes, args.cpu_stride)
