@@ -15,7 +15,7 @@ constexpr int kMaxBigFactors = 7;    // distinct primes >= 7 of a uint32 (7*11*.
 constexpr int kQueueCap = 128;       // per-wave queue of windows that outlive the dense primes
 constexpr int kDeepCounters = 128;   // per-wave LDS counters for the first deep primes
 constexpr int kWheel = 30;           // 2*3*5
-constexpr int kWheelSubsets = 9;     // subsets of {2,3,5}, then an all-ones row for idle lanes
+constexpr int kWheelSubsets = 9;     // subsets of {2,3,5}, then an all-zero row for idle lanes
 constexpr int kIdleSubset = 8;
 constexpr int kBucketChunk = 8192;   // rows regrouped by factor count within each chunk
 // Multiple patterns: for each prime l in 7..61, l entries (entry d, the

@@ -4,8 +4,8 @@
 // an order that groups them by number of prime factors) and walks the columns
 // q in windows of 64, so one 64-bit mask per lane holds the state of 64 pairs.
 // Per window:
-//   1. coprimality (Conjecture 1.1 domain): a wheel lookup clears the q sharing
-//      a factor 2, 3 or 5 with p, and each prime factor >= 7 of p clears its
+//   1. coprimality (Conjecture 1.1 domain): a wheel lookup gives the q sharing
+//      no factor 2, 3 or 5 with p, and each prime factor >= 7 of p clears its
 //      multiples by a shifted bit pattern;
 //   2. dense primes: for the first K non-trivial primes r (ascending) one LDS
 //      read fetches u_r(p mod r, q mod r) for all 64 columns at once, the
@@ -186,6 +186,9 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
     unsigned long long *pairs_rep = P.pairs + (uint64_t)rep * P.rep_stride_pairs;
     uint32_t ri = 0;   // request holding the current unit
 
+    // per lane: coprime pairs seen, and pairs left after each dense prime (the
+    // two 32-bit halves of a window's mask counted separately, so that each
+    // popcount accumulates in one instruction)
     uint32_t left[KD + 1], left_hi[KD + 1];
     for (int k = 0; k <= KD; ++k) { left[k] = 0; left_hi[k] = 0; }
     uint32_t npairs = 0, npairs_hi = 0;
@@ -468,7 +471,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
                 kq[k] = uni(mulr(modr(qs, r, P.dm[k]), P.dinv[k], r, P.dm[k]));
                 lb[k] = P.doff[k] + (modr(p, r, P.dm[k]) * (r + kDenseExt) + kq[k]) * 8;
             }
-            uint32_t kk8 = 0;
+            uint32_t kk8 = 0;   // 8 x window within its group of kDenseExt (wave-uniform)
             uint32_t o30 = uni(qs % kWheel);
 
             // factor l of p: fo = distance from the window start to the next
@@ -490,15 +493,19 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
             }
 
             // ---- windows ----
+            // Window k: columns qb .. qb + 63 of the lane's row.  The wheel word
+            // holds the columns coprime to p's factors 2, 3, 5; each factor >= 7
+            // clears its multiples; then the dense primes, whose entries for
+            // window kk of the current group are kk8 = 8 kk bytes past lb[d].
             const uint32_t nwu = uni(nw);   // keeps the loop exit scalar
             for (uint32_t k = 0; k < nwu; ++k) {
                 const uint32_t qb = qs + k * kWave;
-                uint64_t nc = lds64(smem, wheel_lane + o30 * 8);
+                uint64_t alive = lds64(smem, wheel_lane + o30 * 8);
     #pragma unroll
                 for (int f = 0; f < MF; ++f) {
                     if ((uint32_t)f < nfmax) {
                         const uint32_t idx = fo[f] < (uint32_t)kWave ? fo[f] : (uint32_t)kWave;
-                        nc |= lds64(smem, fb[f] + idx * 8);
+                        alive &= ~lds64(smem, fb[f] + idx * 8);
                         // next window: the distance drops by 64 mod l, or
                         // wraps past a multiple (fo + l - fd < l, no overflow
                         // for any l < 2^32)
@@ -506,7 +513,6 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
                         fo[f] = fo[f] < fd[f] ? t + fl[f] : t;
                     }
                 }
-                uint64_t alive = ~nc;
                 if (k < k_lo || k >= k_hi) {
                     const uint32_t below = rlo > qb ? rlo - qb : 0;
                     const uint32_t upto = rhi >= qb ? rhi - qb + 1 : 0;
@@ -523,6 +529,8 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
                 }
                 kk8 += 8;
                 if (kk8 == kDenseExt * 8) {
+                    // the group is done: fold back to the next group's first
+                    // entry, kq + kDenseExt mod r (kept below r)
                     kk8 = 0;
     #pragma unroll
                     for (int d = 0; d < KD; ++d) {

@@ -169,13 +169,14 @@ __global__ void dense_windows_kernel(const uint32_t *pr, const uint32_t *voff,
 }
 
 // Coprimality wheel: entry s*30 + o has bit j set when o + j is divisible by
-// one of the primes of subset s of {2, 3, 5} (bit 0 = 2, bit 1 = 3, bit 2 = 5);
-// row 8 is all ones (a lane without a row keeps no pairs).
+// none of the primes of subset s of {2, 3, 5} (bit 0 = 2, bit 1 = 3, bit 2 =
+// 5), i.e. the columns such a row keeps; row 8 is all zero (a lane without a
+// row keeps no pairs).
 __global__ void wheel_kernel(uint64_t *out) {
     const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= kWheelSubsets * kWheel) return;
     const uint32_t s = e / kWheel, o = e % kWheel;
-    if (s == kIdleSubset) { out[e] = ~0ull; return; }
+    if (s == kIdleSubset) { out[e] = 0; return; }
     const uint32_t sp[3] = {2, 3, 5};
     uint64_t w = 0;
     for (uint32_t j = 0; j < 64; ++j) {
@@ -184,7 +185,7 @@ __global__ void wheel_kernel(uint64_t *out) {
             if (((s >> k) & 1) && (o + j) % sp[k] == 0) hit = true;
         if (hit) w |= 1ull << j;
     }
-    out[e] = w;
+    out[e] = ~w;
 }
 
 __constant__ uint32_t kPatPrimes[15] = {7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47, 53, 59, 61};
