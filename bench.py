@@ -195,12 +195,8 @@ def run_cpu_baseline(reqs, primes, stride):
     for rect in sample[:8]:
         pairs1 += oracle.sieve(*rect, primes, cap=1 << 16, threads=1)["n_pairs"]
     dt1 = time.time() - t1
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
-    except OSError:
-        pass
+    host = host_cpu()
+    model = host.get("Model name", "")
     return dict(value=pairs / dt, unit="coprime pairs/s", cores=threads, kind="oracle",
                 sample="every %d%s of the 4096 batched rectangles (%d rectangles, %d coprime "
                        "pairs) in %.1f s; tables excluded"
@@ -209,7 +205,65 @@ def run_cpu_baseline(reqs, primes, stride):
                           len(sample), pairs, dt),
                 single_core={"value": pairs1 / dt1, "sample": "the first 8 of those rectangles "
                              "(%d coprime pairs) in %.1f s" % (pairs1, dt1)},
-                cpu_model=model, host_threads=os.cpu_count())
+                cpu_model=model, host=host)
+
+
+def host_cpu():
+    """nproc and the lscpu model line of this host."""
+    import subprocess
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["nproc"] = int(subprocess.run(["nproc"], capture_output=True, text=True).stdout)
+        for ln in subprocess.run(["lscpu"], capture_output=True, text=True).stdout.splitlines():
+            k, _, v = ln.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core",
+                             "CPU max MHz"):
+                info[k.strip()] = v.strip()
+    except (OSError, ValueError):
+        pass
+    return info
+
+
+def cpu_full():
+    """The CPU-baseline plan of the three plain squares: the oracle (tables
+    built first and excluded) on [1, 200]^2 / 3..31, [1, 1e4]^2 / 3..97 and
+    [1, 1e5]^2 / 3..997 in full on all host threads, and on one thread (the
+    largest square on one thread over every 32nd row, scaled, as a full run
+    would take about ten minutes)."""
+    import oracle
+    from paper_1601_00636_amd import workloads as wl
+    out = {"host": host_cpu(), "kind": "oracle", "runs": {}}
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    for name in ("c1", "c2", "c3"):
+        p0, p1, q0, q1, primes = wl.square(name)
+        t = time.time()
+        for r in primes:
+            oracle.table(r)
+        t_tab = time.time() - t
+        t = time.time()
+        res = oracle.sieve(p0, p1, q0, q1, primes, cap=1 << 16, threads=threads)
+        dt = time.time() - t
+        one = {}
+        if name != "c3":
+            t = time.time()
+            r1 = oracle.sieve(p0, p1, q0, q1, primes, cap=1 << 16, threads=1)
+            d1 = time.time() - t
+            one = {"seconds": d1, "pairs_per_s": r1["n_pairs"] / d1, "sample": "full"}
+        else:
+            t = time.time()
+            n1 = 0
+            for row in range(p0, p1 + 1, 32):
+                n1 += oracle.sieve(row, row, q0, q1, primes, cap=1 << 16, threads=1)["n_pairs"]
+            d1 = time.time() - t
+            one = {"seconds": d1, "pairs_per_s": n1 / d1,
+                   "sample": "every 32nd row (%d coprime pairs)" % n1}
+        out["runs"][name] = {"n_pairs": int(res["n_pairs"]), "survivors": int(res["n_survivors"]),
+                             "tables_seconds": t_tab, "all_threads": {"threads": threads,
+                             "seconds": dt, "pairs_per_s": res["n_pairs"] / dt},
+                             "one_thread": one}
+        print(name, json.dumps(out["runs"][name]), file=sys.stderr, flush=True)
+    print(json.dumps(out))
+    return 0
 
 
 def calibrate_copy():
@@ -346,9 +400,14 @@ def main():
                     help="only run the region scan of the paper's section 6 (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="only run the oracle on the three plain squares in full, on all host "
+                         "threads and on one (the CPU-baseline plan; minutes of host time)")
     args = ap.parse_args()
     if args.calibrate_copy:
         return calibrate_copy()
+    if args.cpu_full:
+        return cpu_full()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: the benchmark runs on exactly one GPU; --gpus %d is not supported "
