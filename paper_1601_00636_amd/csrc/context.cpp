@@ -411,10 +411,14 @@ int launch_reqs(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboi
     return CUBOID_OK;
 }
 
-int ensure_scratch(cuboid_ctx *ctx, uint32_t n_req, uint32_t nc, uint64_t surv_cap) {
+int ensure_scratch(cuboid_ctx *ctx, uint32_t n_req, uint32_t nc, uint64_t surv_cap,
+                   uint64_t units) {
     // counter replicas spread the end-of-wave atomics of one request over
-    // several addresses; as many as fit the budget, at most 64
+    // several addresses: about one per 64 units of the launch (a small launch
+    // has few waves to flush and its replicas would only cost summing), at
+    // most 64 and as many as fit the budget
     uint32_t rep = 64;
+    while (rep > 1 && (uint64_t)rep * 64 > units) rep >>= 1;
     while (rep > 1 && (uint64_t)rep * n_req * (nc + 1) * 8 > kReplicaBytes) rep >>= 1;
     ctx->n_rep = rep;
     ctx->rep_stride_counts = (uint64_t)n_req * nc;
@@ -429,17 +433,9 @@ int ensure_scratch(cuboid_ctx *ctx, uint32_t n_req, uint32_t nc, uint64_t surv_c
 }
 
 int zero_scratch(cuboid_ctx *ctx, uint32_t n_req, uint32_t nc, hipStream_t s) {
-    HIPCHK(launch_fill_u64((uint64_t *)ctx->counts.p, (uint64_t)ctx->n_rep * n_req * nc, 0, s));
-    HIPCHK(launch_fill_u64((uint64_t *)ctx->pairs.p, (uint64_t)ctx->n_rep * n_req, 0, s));
-    HIPCHK(launch_fill_u64((uint64_t *)ctx->surv_n.p, 1, 0, s));
-    return CUBOID_OK;
-}
-
-int reduce_scratch(cuboid_ctx *ctx, uint32_t n_req, uint32_t nc, hipStream_t s) {
-    HIPCHK(launch_reduce_replicas((unsigned long long *)ctx->counts.p, (uint64_t)n_req * nc,
-                                  ctx->n_rep, ctx->rep_stride_counts, s));
-    HIPCHK(launch_reduce_replicas((unsigned long long *)ctx->pairs.p, n_req, ctx->n_rep,
-                                  ctx->rep_stride_pairs, s));
+    HIPCHK(launch_clear3((uint64_t *)ctx->counts.p, (uint64_t)ctx->n_rep * n_req * nc,
+                         (uint64_t *)ctx->pairs.p, (uint64_t)ctx->n_rep * n_req,
+                         (uint64_t *)ctx->surv_n.p, 1, s));
     return CUBOID_OK;
 }
 
@@ -500,7 +496,10 @@ int sieve_core(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid
     // caller's prime order (col: the counter of each caller prime, -1 for a
     // trivial one), gathered on the device
     const uint32_t width = col ? (uint32_t)col->size() : nc;
-    int st = ensure_scratch(ctx, n_slots, nc, surv_cap);
+    uint64_t units = 0;
+    for (const ReqDesc &r : reqs)
+        units += (((uint64_t)r.p1 - r.p0 + 64) / 64) * (((uint64_t)r.q1 - r.q0 + 64) / 64);
+    int st = ensure_scratch(ctx, n_slots, nc, surv_cap, units);
     if (st) return st;
     uint32_t pmax = 0;
     for (auto &r : reqs) pmax = std::max(pmax, r.p1);
@@ -580,31 +579,33 @@ int sieve_core(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid
                 if (st) return st;
             }
         }
-        st = reduce_scratch(ctx, n_slots, nc, s);
-        if (st) return st;
-        const void *csrc = ctx->counts.p;
-        if (col && ncount) {
+        // replica sums, the caller's prime order and the survivor count in
+        // one kernel, into an output block [counts | pairs | survivor count]
+        // that comes back in one copy (or counts and pairs into the caller's
+        // device buffers, only the survivor count staged)
+        if (col && width) {
             HIPCHK(ctx->colbuf.ensure(width * 4));
-            if (!dev) HIPCHK(ctx->gathered.ensure(ncount * 8));
-            // the destination is taken after the ensure: growing reallocates
-            void *gdst = dev ? (void *)dev->counts : ctx->gathered.p;
             HIPCHK(hipMemcpyAsync(ctx->colbuf.p, col->data(), width * 4, hipMemcpyHostToDevice, s));
-            HIPCHK(launch_gather_counts((const unsigned long long *)ctx->counts.p,
-                                        (const int32_t *)ctx->colbuf.p, n_slots, nc, width,
-                                        (unsigned long long *)gdst, s));
-            csrc = gdst;
         }
-        // results through pinned staging (counts, pairs, survivor count), or
-        // into the caller's device buffers with only the survivor count staged
-        HIPCHK(ctx->result_stage.ensure((ncount + n_slots + 1) * 8));
+        const uint64_t small_sort = dev ? 0 : std::min<uint64_t>(kSmallSort, surv_cap);
+        const size_t out_bytes = (ncount + n_slots + 1 + 2 * small_sort) * 8;
+        HIPCHK(ctx->gathered.ensure(out_bytes));
+        HIPCHK(ctx->result_stage.ensure(out_bytes));
+        unsigned long long *ob = (unsigned long long *)ctx->gathered.p;
+        unsigned long long *on = dev ? ob : ob + ncount + n_slots;
+        HIPCHK(launch_finish((const unsigned long long *)ctx->counts.p,
+                             (const unsigned long long *)ctx->pairs.p, ctx->n_rep,
+                             ctx->rep_stride_counts, ctx->rep_stride_pairs,
+                             col ? (const int32_t *)ctx->colbuf.p : nullptr, n_slots, nc, width,
+                             dev ? (unsigned long long *)dev->counts : ob,
+                             dev ? (unsigned long long *)dev->pairs : ob + ncount,
+                             (const unsigned long long *)ctx->surv_n.p, on,
+                             (const SurvEntry *)ctx->surv.p, small_sort, (SurvEntry *)(on + 1), s));
         uint64_t *rs = (uint64_t *)ctx->result_stage.p;
-        if (ncount && !dev)
-            HIPCHK(hipMemcpyAsync(rs, csrc, ncount * 8, hipMemcpyDeviceToHost, s));
         if (dev)
-            HIPCHK(launch_copy_u64(dev->pairs, (const uint64_t *)ctx->pairs.p, n_slots, s));
+            HIPCHK(hipMemcpyAsync(rs + ncount + n_slots, on, 8, hipMemcpyDeviceToHost, s));
         else
-            HIPCHK(hipMemcpyAsync(rs + ncount, ctx->pairs.p, (size_t)n_slots * 8, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(rs + ncount + n_slots, ctx->surv_n.p, 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(rs, ob, out_bytes, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
     }
     const uint64_t *stage = (const uint64_t *)ctx->result_stage.p;
@@ -615,7 +616,13 @@ int sieve_core(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboid
     out->pairs = dev ? nullptr : stage + ncount;
     out->n_surv = stage[ncount + n_slots];
     out->surv.clear();
-    if (out->n_surv > 0 && out->n_surv <= surv_cap) {
+    // with host results the finishing kernel has sorted and downloaded up to
+    // kSmallSort survivors already, behind the survivor count
+    const uint64_t sorted_small = dev ? 0 : std::min<uint64_t>(kSmallSort, surv_cap);
+    if (out->n_surv > 0 && out->n_surv <= sorted_small) {
+        const SurvEntry *e = (const SurvEntry *)(stage + ncount + n_slots + 1);
+        out->surv.assign(e, e + out->n_surv);
+    } else if (out->n_surv > 0 && out->n_surv <= surv_cap) {
         st = dev ? place_survivors(ctx, out->n_surv, *dev, s)
                  : fetch_survivors(ctx, out->n_surv, &out->surv, s);
         if (st) return st;

@@ -1,17 +1,21 @@
 // Batched sieve as one HIP graph launch.
 //
 // A batch over resident rows is the fixed sequence: upload of the request
-// block, clears of the counter replicas and survivor count, regrouping of rows
-// by factor count, the sweep, the replica sums, and the download of counts,
-// pair counts and survivor count.  The sizes that vary from batch to batch
+// block, one clear of the counter replicas and survivor count, regrouping of
+// rows by factor count (when some request is regrouped), the sweep, one
+// finishing kernel (replica sums, counts in the caller's prime order, the
+// survivor count, and for results in host memory up to kSmallSort survivors
+// sorted) and one download of its output block, so that a call with few
+// survivors needs no second round trip.  The sizes that vary from batch to batch
 // (unit count, regrouping chunks) travel in the request block's header and the
 // kernels read them from there, so one captured graph serves every batch with
 // the same request count, tables, tuning and buffers.  Graphs are cached per
 // context (least recently used out) and keyed by every pointer and size they
 // bake in.
 //
-// The graph is a parent of three captured parts (before / sweep / after) so
-// that event-record nodes can bracket the sweep for per-call kernel timing.
+// With per-call timing on the graph is a parent of three captured parts
+// (before / sweep / after) so that event-record nodes can bracket the sweep;
+// otherwise it is one flat capture, which is cheaper to launch.
 // Clears are fill kernels: no memset nodes.
 #include <string.h>
 
@@ -75,8 +79,10 @@ struct GraphArgs {
     Layout L;
     uint32_t n, n_slots, nc, np, grid;
     bool gather;                  // counts come back in the caller's prime order
+    bool bucket;                  // some request's rows are regrouped
     uint64_t *dcounts;            // device destinations (cuboid_sieve_batch_dev), else null:
     uint64_t *dpairs;             //   results go to the pinned result staging
+    uint64_t small_sort;          // survivors sorted and downloaded in the graph (0: none)
     size_t lds;
     uint32_t max_p;
     bool timing;
@@ -88,53 +94,64 @@ hipError_t build_graph(cuboid_ctx *ctx, const GraphArgs &a, hipStream_t s, Batch
     const uint64_t nout = (uint64_t)ns * (a.gather ? a.np : nc);
     hipGraph_t pre = nullptr, sweep = nullptr, post = nullptr, parent = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipError_t e = capture_part(s, &pre, [&]() -> hipError_t {
+    auto record_pre = [&]() -> hipError_t {
         hipError_t r = hipMemcpyAsync(a.block, a.stage, a.L.bytes, hipMemcpyHostToDevice, s);
-        if (r == hipSuccess) r = launch_fill_u64((uint64_t *)ctx->counts.p, (uint64_t)ctx->n_rep * ncount, 0, s);
-        if (r == hipSuccess) r = launch_fill_u64((uint64_t *)ctx->pairs.p, (uint64_t)ctx->n_rep * ns, 0, s);
-        if (r == hipSuccess) r = launch_fill_u64((uint64_t *)ctx->surv_n.p, 2, 0, s);
         if (r == hipSuccess)
+            r = launch_clear3((uint64_t *)ctx->counts.p, (uint64_t)ctx->n_rep * ncount,
+                              (uint64_t *)ctx->pairs.p, (uint64_t)ctx->n_rep * ns,
+                              (uint64_t *)ctx->surv_n.p, 2, s);
+        if (r == hipSuccess && a.bucket)
             r = launch_bucket_rows((const ReqDesc *)(a.block + a.L.o_desc), n,
                                    (const uint64_t *)(a.block + a.L.o_cpre), 0,
                                    (const uint64_t *)(a.block + a.L.o_rpre), a.order, s,
                                    (const uint64_t *)a.block + 1, kBucketGrid);
         return r;
-    });
-    if (e == hipSuccess)
-        e = capture_part(s, &sweep, [&]() { return launch_sweep(a.P, (int)a.grid, a.lds, a.max_p, s); });
-    if (e == hipSuccess)
-        e = capture_part(s, &post, [&]() -> hipError_t {
-            hipError_t r = launch_reduce_replicas((unsigned long long *)ctx->counts.p, ncount,
-                                                  ctx->n_rep, ctx->rep_stride_counts, s);
-            if (r == hipSuccess)
-                r = launch_reduce_replicas((unsigned long long *)ctx->pairs.p, ns, ctx->n_rep,
-                                           ctx->rep_stride_pairs, s);
-            const void *csrc = ctx->counts.p;
-            if (r == hipSuccess && a.gather && nout) {
-                void *gdst = a.dcounts ? (void *)a.dcounts : ctx->gathered.p;
-                r = launch_gather_counts((const unsigned long long *)ctx->counts.p,
-                                         (const int32_t *)(a.block + a.L.o_col), ns, nc, a.np,
-                                         (unsigned long long *)gdst, s);
-                csrc = gdst;
-            }
-            // no counters when every prime is trivial; capture refuses empty copies
-            if (r == hipSuccess && nout && !a.dcounts)
-                r = hipMemcpyAsync(a.result, csrc, nout * 8, hipMemcpyDeviceToHost, s);
-            if (r == hipSuccess && a.dpairs)
-                r = launch_copy_u64(a.dpairs, (const uint64_t *)ctx->pairs.p, ns, s);
+    };
+    auto record_sweep = [&]() { return launch_sweep(a.P, (int)a.grid, a.lds, a.max_p, s); };
+    auto record_post = [&]() -> hipError_t {
+            // output block (device, downloaded whole into the result staging):
+            // [nout counts | ns pairs | survivor count | small_sort survivors];
+            // with device destinations only the survivor count is in it
+            unsigned long long *ob = (unsigned long long *)ctx->gathered.p;
+            unsigned long long *oc = a.dcounts ? (unsigned long long *)a.dcounts : ob;
+            unsigned long long *op = a.dpairs ? (unsigned long long *)a.dpairs : ob + nout;
+            unsigned long long *on = a.dcounts ? ob : ob + nout + ns;
+            hipError_t r = launch_finish((const unsigned long long *)ctx->counts.p,
+                                         (const unsigned long long *)ctx->pairs.p, ctx->n_rep,
+                                         ctx->rep_stride_counts, ctx->rep_stride_pairs,
+                                         a.gather ? (const int32_t *)(a.block + a.L.o_col) : nullptr,
+                                         ns, nc, a.gather ? a.np : nc, oc, op,
+                                         (const unsigned long long *)ctx->surv_n.p, on,
+                                         (const SurvEntry *)ctx->surv.p, a.small_sort,
+                                         (SurvEntry *)(on + 1), s);
+            if (r == hipSuccess && a.dcounts)
+                r = hipMemcpyAsync(a.result + nout + ns, on, 8, hipMemcpyDeviceToHost, s);
             else if (r == hipSuccess)
-                r = hipMemcpyAsync(a.result + nout, ctx->pairs.p, (size_t)ns * 8,
+                r = hipMemcpyAsync(a.result, ob, (nout + ns + 1 + 2 * a.small_sort) * 8,
                                    hipMemcpyDeviceToHost, s);
-            if (r == hipSuccess)
-                r = hipMemcpyAsync(a.result + nout + ns, ctx->surv_n.p, 8, hipMemcpyDeviceToHost, s);
+            return r;
+        };
+    hipError_t e = hipSuccess;
+    if (!a.timing) {
+        // one flat capture (a nested graph costs more to launch)
+        e = capture_part(s, &parent, [&]() -> hipError_t {
+            hipError_t r = record_pre();
+            if (r == hipSuccess) r = record_sweep();
+            if (r == hipSuccess) r = record_post();
             return r;
         });
-    if (e == hipSuccess) e = hipGraphCreate(&parent, 0);
-    if (e == hipSuccess) {
+    } else {
+        // three captured parts with event-record nodes around the sweep
+        e = capture_part(s, &pre, record_pre);
+        if (e == hipSuccess) e = capture_part(s, &sweep, record_sweep);
+        if (e == hipSuccess) e = capture_part(s, &post, record_post);
+        if (e == hipSuccess) e = hipGraphCreate(&parent, 0);
+    }
+    if (e == hipSuccess && a.timing) {
         hipGraphNode_t prev = nullptr, node = nullptr;
         e = hipGraphAddChildGraphNode(&node, parent, nullptr, 0, pre);
         prev = node;
-        if (e == hipSuccess && a.timing) {
+        if (e == hipSuccess) {
             e = hipGraphAddEventRecordNode(&node, parent, &prev, 1, ctx->ev_sweep0);
             prev = node;
         }
@@ -142,7 +159,7 @@ hipError_t build_graph(cuboid_ctx *ctx, const GraphArgs &a, hipStream_t s, Batch
             e = hipGraphAddChildGraphNode(&node, parent, &prev, 1, sweep);
             prev = node;
         }
-        if (e == hipSuccess && a.timing) {
+        if (e == hipSuccess) {
             e = hipGraphAddEventRecordNode(&node, parent, &prev, 1, ctx->ev_sweep1);
             prev = node;
         }
@@ -207,9 +224,13 @@ int run_batch_graph(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const c
     // the previous reader of the staging buffers on this stream is done once
     // the stream is idle
     if (hipStreamSynchronize(s) != hipSuccess) return CUBOID_E_DEVICE;
+    // survivors sorted inside the graph for results in host memory: at most
+    // kSmallSort, and no more than the survivor scratch holds
+    const uint64_t small_sort = dev ? 0 : std::min<uint64_t>(kSmallSort, surv_cap);
+    const size_t out_bytes = (nout + n_slots + 1 + 2 * small_sort) * 8;
     if (ctx->gstage.ensure(L.bytes) != hipSuccess || ctx->gblock.ensure(L.bytes) != hipSuccess ||
-        ctx->result_stage.ensure((nout + n_slots + 1) * 8) != hipSuccess ||
-        (col && ctx->gathered.ensure(nout * 8 + 8) != hipSuccess))
+        ctx->result_stage.ensure(out_bytes) != hipSuccess ||
+        ctx->gathered.ensure(out_bytes) != hipSuccess)
         return CUBOID_E_DEVICE;
     unsigned char *st = (unsigned char *)ctx->gstage.p;
     const uint64_t hdr[4] = {sh.units, sh.n_chunks, 0, 0};
@@ -230,8 +251,10 @@ int run_batch_graph(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const c
     a.nc = nc;
     a.np = np;
     a.gather = col != nullptr;
+    a.bucket = sh.n_order > 0;
     a.dcounts = dev ? dev->counts : nullptr;
     a.dpairs = dev ? dev->pairs : nullptr;
+    a.small_sort = small_sort;
     a.grid = tun.workgroups;
     a.lds = lds;
     a.max_p = sh.max_p;
@@ -253,6 +276,9 @@ int run_batch_graph(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const c
     put(&key, n_slots);
     put(&key, np);
     put(&key, (uint32_t)a.gather);
+    put(&key, (uint32_t)a.bucket);
+    put(&key, a.small_sort);
+    put(&key, (const void *)ctx->surv.p);
     put(&key, (const void *)ctx->gathered.p);
     put(&key, (const void *)a.dcounts);
     put(&key, (const void *)a.dpairs);

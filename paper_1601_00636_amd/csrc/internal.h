@@ -169,6 +169,10 @@ hipError_t launch_gather_counts(const unsigned long long *counts, const int32_t 
                                 unsigned long long *out, hipStream_t s);
 hipError_t launch_reduce_replicas(unsigned long long *buf, uint64_t n, uint32_t n_rep,
                                   uint64_t stride, hipStream_t s);
+// zero a[na], b[nb], c[nc] in one launch
+hipError_t launch_clear3(uint64_t *a, uint64_t na, uint64_t *b, uint64_t nb, uint64_t *c,
+                         uint64_t nc, hipStream_t s);
+
 // max_p: the largest row coordinate of the launch (selects the factor slots)
 // factor slots the sweep reserves per row for rows up to max_p (4, 5 or 7)
 int sweep_factor_slots(uint32_t max_p);
@@ -178,6 +182,17 @@ hipError_t sweep_max_lds(size_t *bytes);
 // sorts n <= cap entries (n read from device) ascending by (req, idx) into out
 hipError_t launch_sort_surv(SurvEntry *a, SurvEntry *tmp, const unsigned long long *n_dev,
                             uint64_t cap, SurvEntry **out, hipStream_t s);
+// Replica sums, counts in the caller's order (col, or canonical when null) and
+// the survivor count n, in one launch: out_counts[n_slots][np],
+// out_pairs[n_slots], *out_n; with small_cap (<= kSmallSort) also the first
+// min(n, small_cap) survivors of surv, sorted, into out_surv.
+constexpr uint64_t kSmallSort = 1024;
+hipError_t launch_finish(const unsigned long long *counts, const unsigned long long *pairs,
+                         uint32_t n_rep, uint64_t stride_c, uint64_t stride_p, const int32_t *col,
+                         uint32_t n_slots, uint32_t nc, uint32_t np, unsigned long long *out_counts,
+                         unsigned long long *out_pairs, const unsigned long long *surv_n,
+                         unsigned long long *out_n, const SurvEntry *surv, uint64_t small_cap,
+                         SurvEntry *out_surv, hipStream_t s);
 
 // ---- root check (kernels_roots.hip) ----
 struct RootCand {

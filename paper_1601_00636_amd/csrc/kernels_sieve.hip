@@ -606,6 +606,70 @@ __global__ void __launch_bounds__(256) block_sort_kernel(SurvEntry *a, const uns
     }
 }
 
+// The results of a sweep in one launch: out_counts[slot][j] = the sum over
+// the n_rep replicas of counter col[j] of the slot (0 where col[j] < 0; the
+// canonical counters, j itself, when col is null), out_pairs[slot] = the sum
+// of the pair-count replicas, *out_n = the survivor count n; with small_cap
+// > 0 block 0 also sorts the first min(n, small_cap) survivors into out_surv
+// (all of them when n <= small_cap).
+__global__ void __launch_bounds__(256) finish_kernel(
+    const unsigned long long *counts, const unsigned long long *pairs, uint32_t n_rep,
+    uint64_t stride_c, uint64_t stride_p, const int32_t *col, uint32_t n_slots, uint32_t nc,
+    uint32_t np, unsigned long long *out_counts, unsigned long long *out_pairs,
+    const unsigned long long *surv_n, unsigned long long *out_n, const SurvEntry *surv,
+    uint32_t small_cap, SurvEntry *out_surv) {
+    const uint64_t ncount = (uint64_t)n_slots * np, n = ncount + n_slots + 1;
+    for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < n;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        if (g < ncount) {
+            const uint64_t slot = g / np;
+            const uint32_t j = (uint32_t)(g - slot * np);
+            const int32_t c = col ? col[j] : (int32_t)j;
+            unsigned long long v = 0;
+            // (unrolled so that the replica loads are in flight together)
+            if (c >= 0) {
+    #pragma unroll 8
+                for (uint32_t r = 0; r < n_rep; ++r) v += counts[r * stride_c + slot * nc + (uint32_t)c];
+            }
+            out_counts[g] = v;
+        } else if (g < ncount + n_slots) {
+            const uint64_t slot = g - ncount;
+            unsigned long long v = 0;
+    #pragma unroll 8
+            for (uint32_t r = 0; r < n_rep; ++r) v += pairs[r * stride_p + slot];
+            out_pairs[slot] = v;
+        } else {
+            *out_n = *surv_n;
+        }
+    }
+    if (blockIdx.x != 0 || small_cap == 0) return;
+    __shared__ SurvEntry sv[kSortTile];
+    const uint64_t m = *surv_n < small_cap ? *surv_n : small_cap;
+    if (m == 0) return;
+    for (uint32_t i = threadIdx.x; i < (uint32_t)kSortTile; i += blockDim.x) {
+        if (i < m) {
+            sv[i] = surv[i];
+        } else {
+            sv[i].idx = ~0ull; sv[i].req = 0xffffffffu; sv[i].pad = 0;
+        }
+    }
+    __syncthreads();
+    for (uint32_t k = 2; k <= (uint32_t)kSortTile; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < (uint32_t)kSortTile; i += blockDim.x) {
+                const uint32_t ixj = i ^ j;
+                if (ixj > i) {
+                    const bool up = (i & k) == 0;
+                    const SurvEntry x = sv[i], y = sv[ixj];
+                    if (up ? surv_less(y, x) : surv_less(x, y)) { sv[i] = y; sv[ixj] = x; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) out_surv[i] = sv[i];
+}
+
 // Merge sorted runs of length L pairwise.  Keys are distinct, so an element's
 // place is its rank in its own run plus the number of smaller keys in the
 // partner run.  A pass with L >= n only copies.
@@ -675,6 +739,23 @@ hipError_t sweep_max_lds(size_t *bytes) {
     if (e != hipSuccess) return e;
     *bytes = (size_t)v;
     return hipSuccess;
+}
+
+hipError_t launch_finish(const unsigned long long *counts, const unsigned long long *pairs,
+                         uint32_t n_rep, uint64_t stride_c, uint64_t stride_p, const int32_t *col,
+                         uint32_t n_slots, uint32_t nc, uint32_t np, unsigned long long *out_counts,
+                         unsigned long long *out_pairs, const unsigned long long *surv_n,
+                         unsigned long long *out_n, const SurvEntry *surv, uint64_t small_cap,
+                         SurvEntry *out_surv, hipStream_t s) {
+    static_assert(kSmallSort == kSortTile, "one sort tile");
+    if (small_cap > kSmallSort || (small_cap && (!surv || !out_surv))) return hipErrorInvalidValue;
+    const uint64_t n = (uint64_t)n_slots * np + n_slots + 1;
+    uint64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(finish_kernel, dim3((unsigned)g), dim3(256), 0, s, counts, pairs, n_rep,
+                       stride_c, stride_p, col, n_slots, nc, np, out_counts, out_pairs, surv_n,
+                       out_n, surv, (uint32_t)small_cap, out_surv);
+    return hipGetLastError();
 }
 
 hipError_t launch_sort_surv(SurvEntry *a, SurvEntry *tmp, const unsigned long long *n_dev,

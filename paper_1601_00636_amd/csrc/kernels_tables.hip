@@ -371,6 +371,19 @@ __global__ void gather_counts_kernel(const unsigned long long *counts, const int
     }
 }
 
+// Zeroes three buffers in one launch (counter replicas, pair-count replicas,
+// survivor count and claim counter).
+__global__ void clear3_kernel(uint64_t *a, uint64_t na, uint64_t *b, uint64_t nb, uint64_t *c,
+                              uint64_t nc) {
+    const uint64_t n = na + nb + nc;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        if (i < na) a[i] = 0;
+        else if (i < na + nb) b[i - na] = 0;
+        else c[i - na - nb] = 0;
+    }
+}
+
 __global__ void reduce_replicas_kernel(unsigned long long *buf, uint64_t n, uint32_t n_rep,
                                        uint64_t stride) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
@@ -382,6 +395,14 @@ __global__ void reduce_replicas_kernel(unsigned long long *buf, uint64_t n, uint
 }
 
 }  // namespace
+
+hipError_t launch_clear3(uint64_t *a, uint64_t na, uint64_t *b, uint64_t nb, uint64_t *c,
+                         uint64_t nc, hipStream_t s) {
+    const uint64_t n = na + nb + nc;
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(clear3_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, a, na, b, nb, c, nc);
+    return hipGetLastError();
+}
 
 hipError_t launch_copy_u64(uint64_t *dst, const uint64_t *src, uint64_t n, hipStream_t s) {
     if (!n) return hipSuccess;
