@@ -412,15 +412,22 @@ typedef struct cuboid_tuning {
                                 LDS cursor), 1 = round-robin pieces per wave,
                                 2 = one shared counter in device memory;
                                 results never depend on it                    */
+    uint32_t piece_units;    /* 64x64 units per piece of schedules 0, 1 and 3
+                                (0 = chosen from the launch size: up to 256,
+                                or 4096 in launches of more than 32 x 4096
+                                units per workgroup); at most 2^20            */
 } cuboid_tuning;
 
 /*
- * Time candidate tunings for `primes` (the last six dense-prime counts that
- * fit in LDS, times grids of 1, 2, 4 and 8 workgroups per compute unit) on a
- * sample rectangle of 32768 x 65536 pairs near 2^19 and keep the fastest for
- * this context; if cache_path is non-NULL the choice is read from
- * / appended to that JSON-lines file, keyed by device architecture and prime
- * set.  Results never depend on the tuning.  out may be NULL.
+ * Time candidate tunings for `primes` on a sample rectangle of 32768 x 65536
+ * pairs near 2^19 and keep the fastest for this context: first the last six
+ * dense-prime counts that fit in LDS times grids of 1, 2, 4 and 8 workgroups
+ * per compute unit, then for the best of those the work sharing (workgroup
+ * pieces of 64, 128, 512, 1024 or 4096 units or chosen by size, round-robin
+ * pieces per wave, the shared counter).  If cache_path is non-NULL the choice
+ * (every field) is read from / appended to that JSON-lines file, keyed by
+ * device architecture and prime set.  Results never depend on the tuning.
+ * out may be NULL.
  */
 int cuboid_autotune(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes,
                     const char *cache_path, cuboid_tuning *out);

@@ -43,7 +43,8 @@ class cuboid_result(ctypes.Structure):
 
 
 class cuboid_tuning(ctypes.Structure):
-    _fields_ = [("dense_primes", u32), ("workgroups", u32), ("lds_budget", u32), ("schedule", u32)]
+    _fields_ = [("dense_primes", u32), ("workgroups", u32), ("lds_budget", u32), ("schedule", u32),
+                ("piece_units", u32)]
 
 
 class cuboid_timing(ctypes.Structure):
@@ -611,15 +612,22 @@ def cuboid_enable_graphs(ctx, on=True):
     _check(_load().cuboid_enable_graphs(ctx, 1 if on else 0), "cuboid_enable_graphs")
 
 
-def cuboid_set_tuning(ctx, primes, dense_primes=None, workgroups=0, lds_budget=0, schedule=0):
+def _tuning(t):
+    return {k: getattr(t, k) for k, _ in cuboid_tuning._fields_}
+
+
+def cuboid_set_tuning(ctx, primes, dense_primes=None, workgroups=0, lds_budget=0, schedule=0,
+                      piece_units=0):
     """No keyword arguments: back to the defaults.  schedule: 0 or 3 workgroup
-    pieces, 1 round-robin pieces per wave, 2 shared counter."""
+    pieces, 1 round-robin pieces per wave, 2 shared counter; piece_units: units
+    per piece (0: chosen by launch size)."""
     pr = _arr(primes, np.uint32)
-    if dense_primes is None and not workgroups and not lds_budget and not schedule:
+    if (dense_primes is None and not workgroups and not lds_budget and not schedule
+            and not piece_units):
         _check(_load().cuboid_set_tuning(ctx, _p(pr, u32), len(pr), None), "cuboid_set_tuning")
         return
     t = cuboid_tuning(0xffffffff if dense_primes is None else int(dense_primes), int(workgroups),
-                      int(lds_budget), int(schedule))
+                      int(lds_budget), int(schedule), int(piece_units))
     _check(_load().cuboid_set_tuning(ctx, _p(pr, u32), len(pr), ctypes.byref(t)),
            "cuboid_set_tuning")
 
@@ -629,8 +637,7 @@ def cuboid_get_tuning(ctx, primes):
     t = cuboid_tuning()
     _check(_load().cuboid_get_tuning(ctx, _p(pr, u32), len(pr), ctypes.byref(t)),
            "cuboid_get_tuning")
-    return dict(dense_primes=t.dense_primes, workgroups=t.workgroups, lds_budget=t.lds_budget,
-                schedule=t.schedule)
+    return _tuning(t)
 
 
 def cuboid_autotune(ctx, primes, cache_path=None):
@@ -639,8 +646,7 @@ def cuboid_autotune(ctx, primes, cache_path=None):
     cp = cache_path.encode() if cache_path else None
     _check(_load().cuboid_autotune(ctx, _p(pr, u32), len(pr), cp, ctypes.byref(t)),
            "cuboid_autotune")
-    return dict(dense_primes=t.dense_primes, workgroups=t.workgroups, lds_budget=t.lds_budget,
-                schedule=t.schedule)
+    return _tuning(t)
 
 
 def cuboid_autotune_for(ctx, primes, sample, cache_path=None):
@@ -652,8 +658,7 @@ def cuboid_autotune_for(ctx, primes, sample, cache_path=None):
     _check(_load().cuboid_autotune_for(ctx, _p(pr, u32), len(pr),
                                        reqa.ctypes.data_as(P(cuboid_request)), reqa.shape[0], cp,
                                        ctypes.byref(t)), "cuboid_autotune_for")
-    return dict(dense_primes=t.dense_primes, workgroups=t.workgroups, lds_budget=t.lds_budget,
-                schedule=t.schedule)
+    return _tuning(t)
 
 
 def cuboid_server_start(ctx, primes, streams=0, max_slots=0, max_launch_units=0,

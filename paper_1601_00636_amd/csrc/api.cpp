@@ -568,6 +568,7 @@ int cuboid_set_tuning(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_primes
     if (tuning->dense_primes > (uint32_t)kKMax && tuning->dense_primes != 0xffffffffu)
         return CUBOID_E_ARG;
     if (tuning->schedule > 3) return CUBOID_E_ARG;
+    if (tuning->piece_units > (1u << 20)) return CUBOID_E_ARG;
     ctx->tunings[sorted] = *tuning;
     return CUBOID_OK;
 }

@@ -1,6 +1,7 @@
-// Autotuner: times the sweep for candidate tunings (number of dense primes K,
-// persistent grid size) on a sample rectangle and keeps the fastest for the
-// prime set.  Choices are cached as JSON lines keyed by device architecture
+// Autotuner: times the sweep for candidate tunings (number of dense primes K
+// and persistent grid size, then for the best of those the work sharing:
+// schedule and piece size) on a sample and keeps the fastest for the prime
+// set.  Choices are cached as JSON lines keyed by device architecture
 // and prime set.  Results never depend on the tuning (the dense primes are an
 // ascending prefix and every count is the first rejecting prime).
 #include <stdio.h>
@@ -47,10 +48,17 @@ bool read_cache(const char *path, const std::string &arch, const std::string &ke
         if (sscanf(pk, "\"dense_primes\": %u", &k) != 1) continue;
         if (sscanf(pw, "\"workgroups\": %u", &w) != 1) continue;
         if (sscanf(pb, "\"lds_budget\": %u", &b) != 1) continue;
+        unsigned sc = 0, pc = 0;   // absent from older lines: the defaults
+        const char *ps = strstr(line, "\"schedule\": ");
+        const char *pp = strstr(line, "\"piece_units\": ");
+        if (ps && sscanf(ps, "\"schedule\": %u", &sc) != 1) continue;
+        if (pp && sscanf(pp, "\"piece_units\": %u", &pc) != 1) continue;
+        if (sc > 3 || pc > (1u << 20)) continue;
         out->dense_primes = k;
         out->workgroups = w;
         out->lds_budget = b;
-        out->schedule = 0;
+        out->schedule = sc;
+        out->piece_units = pc;
         found = true;   // the last matching line wins
     }
     fclose(f);
@@ -63,8 +71,9 @@ void append_cache(const char *path, const std::string &arch, const std::string &
     if (!f) return;
     fprintf(f,
             "{\"arch\": \"%s\", \"primes\": \"%s\", \"dense_primes\": %u, \"workgroups\": %u, "
-            "\"lds_budget\": %u, \"sample_ms\": %.4f}\n",
-            arch.c_str(), key.c_str(), t.dense_primes, t.workgroups, t.lds_budget, ms);
+            "\"lds_budget\": %u, \"schedule\": %u, \"piece_units\": %u, \"sample_ms\": %.4f}\n",
+            arch.c_str(), key.c_str(), t.dense_primes, t.workgroups, t.lds_budget, t.schedule,
+            t.piece_units, ms);
     fclose(f);
 }
 
@@ -90,27 +99,47 @@ int tune(cuboid_ctx *ctx, const std::vector<uint32_t> &sorted, const cuboid_requ
     ctx->timing = true;
     double best_ms = 1e30;
     best.dense_primes = 0; best.workgroups = cus; best.lds_budget = budget; best.schedule = 0;
+    best.piece_units = 0;
+    // the best sweep time of three runs under tuning t
+    auto time_of = [&](const cuboid_tuning &t, double *ms) -> int {
+        ctx->tunings[sorted] = t;
+        *ms = 1e30;
+        for (int rep = 0; rep < 3; ++rep) {
+            int r = sieve_rects(ctx, sorted, sample, n_sample, 1 << 16, ctx->stream, &ctx->h_out);
+            if (r == CUBOID_E_LIMIT || r == CUBOID_E_CAPACITY) r = CUBOID_OK;
+            if (r) return r;
+            *ms = std::min(*ms, ctx->last.sweep_ms);
+        }
+        return CUBOID_OK;
+    };
     const uint32_t klo = kmax > 5 ? kmax - 5 : 0;
     // one workgroup fills a compute unit's LDS, so grids beyond the CU count
     // run as successive waves of workgroups: smaller pieces that even out
     // the finishing times of unequal units
     const uint32_t wgs[4] = {cus, 2 * cus, 4 * cus, 8 * cus};
-    for (uint32_t K = klo; K <= kmax; ++K) {
+    for (uint32_t K = klo; K <= kmax && !st; ++K) {
         for (uint32_t w : wgs) {
             cuboid_tuning t;
             t.dense_primes = K; t.workgroups = w; t.lds_budget = budget; t.schedule = 0;
-            ctx->tunings[sorted] = t;
-            double ms_best = 1e30;
-            for (int rep = 0; rep < 3; ++rep) {
-                st = sieve_rects(ctx, sorted, sample, n_sample, 1 << 16, ctx->stream, &ctx->h_out);
-                if (st == CUBOID_E_LIMIT || st == CUBOID_E_CAPACITY) st = CUBOID_OK;
-                if (st) break;
-                ms_best = std::min(ms_best, ctx->last.sweep_ms);
-            }
+            t.piece_units = 0;
+            double ms = 0;
+            st = time_of(t, &ms);
             if (st) break;
-            if (ms_best < best_ms) { best_ms = ms_best; best = t; }
+            if (ms < best_ms) { best_ms = ms; best = t; }
         }
-        if (st) break;
+    }
+    // the work sharing for the best K and grid: workgroup pieces of fixed
+    // sizes, round-robin pieces per wave, the shared counter
+    const uint32_t shares[8][2] = {{0, 64}, {0, 128}, {0, 512}, {0, 1024},
+                                   {0, 4096}, {1, 0}, {1, 64}, {2, 0}};
+    const cuboid_tuning base = best;
+    for (int i = 0; i < 8 && !st; ++i) {
+        cuboid_tuning t = base;
+        t.schedule = shares[i][0];
+        t.piece_units = shares[i][1];
+        double ms = 0;
+        st = time_of(t, &ms);
+        if (!st && ms < best_ms) { best_ms = ms; best = t; }
     }
     ctx->timing = saved_timing;
     if (st) {

@@ -279,7 +279,10 @@ cuboid_tuning tuning_for(cuboid_ctx *ctx, const std::vector<uint32_t> &primes, c
     cuboid_tuning t;
     auto it = ctx->tunings.find(primes);
     if (it != ctx->tunings.end()) t = it->second;
-    else { t.dense_primes = 0xffffffffu; t.workgroups = 0; t.lds_budget = 0; t.schedule = 0; }
+    else {
+        t.dense_primes = 0xffffffffu; t.workgroups = 0; t.lds_budget = 0; t.schedule = 0;
+        t.piece_units = 0;
+    }
     // the dense tables and the sweep's fixed LDS must fit one workgroup; by
     // default the tables take all of the LDS left
     const uint32_t room = ctx->max_lds > kSweepFixedLds ? (uint32_t)(ctx->max_lds - kSweepFixedLds) : 0;
@@ -398,6 +401,7 @@ int launch_reqs(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const cuboi
     SweepParams P =
         sweep_params(ctx, pl, ds, (const ReqDesc *)ctx->reqbuf.p, n, sh.units, surv_cap);
     P.schedule = tun.schedule;
+    P.piece = tun.piece_units;
     for (const ReqDesc &d : reqs) P.band_split |= (d.flags & kReqBandSplit) ? 1u : 0u;
     const size_t lds = (size_t)ds.words * 8 + kSweepFixedLds;
     if (lds > ctx->max_lds) return CUBOID_E_LIMIT;

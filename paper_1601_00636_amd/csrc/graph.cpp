@@ -261,6 +261,7 @@ int run_batch_graph(cuboid_ctx *ctx, const Plan &pl, const DenseSet &ds, const c
     a.timing = ctx->timing;
     a.P = sweep_params(ctx, pl, ds, (const ReqDesc *)(a.block + L.o_desc), n, 0, surv_cap);
     a.P.schedule = tun.schedule;
+    a.P.piece = tun.piece_units;
     for (const ReqDesc &d : reqs) a.P.band_split |= (d.flags & kReqBandSplit) ? 1u : 0u;
     a.P.units_dev = (const unsigned long long *)a.block;
 

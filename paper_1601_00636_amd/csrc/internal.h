@@ -97,6 +97,7 @@ struct SweepParams {
     const ReqDesc *req;
     uint32_t n_req;
     uint32_t schedule;                   // 0 or 3 workgroup pieces, 1 round-robin pieces, 2 shared counter
+    uint32_t piece;                      // units per piece of schedules 0, 1, 3 (0: chosen by size)
     uint64_t n_units;
     unsigned long long *counts;          // [n_rep][slot][nc], canonical ascending order
     unsigned long long *pairs;           // [n_rep][slot]

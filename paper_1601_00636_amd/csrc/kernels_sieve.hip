@@ -284,7 +284,8 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
     // about eight pieces per wave, at most kPiece units each (a small launch
     // deals small pieces, so that every wave gets some)
     const uint64_t per_wave = n_units / nwaves / 8;
-    const uint64_t psize = per_wave < 1 ? 1 : (per_wave < kPiece ? per_wave : kPiece);
+    const uint64_t psize =
+        P.piece ? P.piece : (per_wave < 1 ? 1 : (per_wave < kPiece ? per_wave : kPiece));
     uint64_t piece = w;
     uint64_t lcur = 0, lend = 0;   // the wave's claimed units of its workgroup's share
     // workgroup pieces: at least kWgPieces per workgroup, of up to kPiece units,
@@ -293,6 +294,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerWG) sweep_kernel(const SweepP
     const uint64_t G = gridDim.x;
     uint64_t wg_ps = n_units / (G * kWgPieces);
     wg_ps = wg_ps >= kBigPiece ? kBigPiece : (wg_ps < 1 ? 1 : (wg_ps < kPiece ? wg_ps : kPiece));
+    if (P.piece) wg_ps = P.piece;   // the tuning's own piece size
     for (;;) {
         uint64_t u = 0, uend = 0;
         bool done = false;

@@ -182,6 +182,7 @@ extern "C" int cuboid_sieve_batch_dev_noalloc(cuboid_ctx *ctx, const cuboid_requ
     P.surv_n = ctl;
     P.claim = ctl + 1;
     P.schedule = tun.schedule;
+    P.piece = tun.piece_units;
     P.band_split = 0;
     HIPCHK(launch_sweep(P, (int)tun.workgroups, lds, sh.max_p, s));
     HIPCHK(launch_reduce_replicas(counts, n * nc, rep, n * nc, s));

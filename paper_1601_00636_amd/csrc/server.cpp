@@ -266,6 +266,7 @@ hipError_t sweep_last(cuboid_server *S, StreamState &st, unsigned long long *cnt
     P.surv_n = (unsigned long long *)st.surv_n.p;
     P.claim = (unsigned long long *)st.surv_n.p + 1;
     P.schedule = S->tun.schedule;
+    P.piece = S->tun.piece_units;
     const size_t lds = (size_t)ds.words * 8 + kSweepFixedLds;
     return launch_sweep(P, (int)S->tun.workgroups, lds, st.last_max_p, st.s);
 }

@@ -37,6 +37,9 @@ def test_autotune_for_a_sample_and_its_cache(ctx, tmp_path):
     cus = _cus(ctx)
     assert t["workgroups"] in (cus, 2 * cus, 4 * cus, 8 * cus)
     assert 0 <= t["dense_primes"] <= 12
+    # the work sharing is one of the candidates
+    assert (t["schedule"], t["piece_units"]) in {(0, 0), (0, 64), (0, 128), (0, 512), (0, 1024),
+                                                 (0, 4096), (1, 0), (1, 64), (2, 0)}
     assert cb.cuboid_get_tuning(ctx, primes)["dense_primes"] == t["dense_primes"]
     for rect in sample:
         _same(cb.cuboid_sieve_range(ctx, *rect, primes, cap=1 << 16),
@@ -49,6 +52,8 @@ def test_autotune_for_a_sample_and_its_cache(ctx, tmp_path):
         cb.cuboid_destroy(other)
     lines = open(cache).read().splitlines()
     assert len(lines) == 1 and "_w3_" in lines[0]     # keyed by the sample too
+    assert '"schedule": %d' % t["schedule"] in lines[0]
+    assert '"piece_units": %d' % t["piece_units"] in lines[0]
     cb.cuboid_set_tuning(ctx, primes)
 
 
@@ -80,3 +85,23 @@ def test_default_tuning_fills_the_lds(ctx):
     sizes = [8 * r * (r + 16) for r in wl.PRIMES_PAPER[:13]]
     k = t["dense_primes"]
     assert sum(sizes[:k]) <= t["lds_budget"] < sum(sizes[:k + 1])
+
+
+def test_cache_lines_without_work_sharing_fields(ctx, tmp_path):
+    # a cache line written before the work-sharing fields existed reads back
+    # with the defaults
+    primes = [11, 13, 17]
+    cache = tmp_path / "old.jsonl"
+    t = cb.cuboid_autotune(ctx, primes, cache_path=str(cache))
+    line = cache.read_text().splitlines()[0]
+    old = line.replace(', "schedule": %d, "piece_units": %d' % (t["schedule"], t["piece_units"]), "")
+    assert old != line
+    cache.write_text(old + "\n")
+    other = cb.cuboid_create(0)
+    try:
+        got = cb.cuboid_autotune(other, primes, cache_path=str(cache))
+    finally:
+        cb.cuboid_destroy(other)
+    assert got["schedule"] == 0 and got["piece_units"] == 0
+    assert got["dense_primes"] == t["dense_primes"] and got["workgroups"] == t["workgroups"]
+    cb.cuboid_set_tuning(ctx, primes)

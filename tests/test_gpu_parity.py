@@ -411,3 +411,26 @@ def test_schedule_out_of_range(ctx):
     with pytest.raises(cb.CuboidError) as e:
         cb.cuboid_set_tuning(ctx, wl.PRIMES_C2, schedule=4)
     assert e.value.status == cb.E_ARG
+    with pytest.raises(cb.CuboidError) as e:
+        cb.cuboid_set_tuning(ctx, wl.PRIMES_C2, piece_units=(1 << 20) + 1)
+    assert e.value.status == cb.E_ARG
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("piece", [1, 7, 64, 4096, 1 << 20])
+def test_piece_sizes(ctx, schedule, piece):
+    # every piece size the tuning allows gives the oracle's results, from one
+    # unit per piece to pieces larger than the whole launch
+    primes = wl.PRIMES_C2
+    cb.cuboid_set_tuning(ctx, primes, schedule=schedule, piece_units=piece)
+    try:
+        assert cb.cuboid_get_tuning(ctx, primes)["piece_units"] == piece
+        for rect in ((1, 3000, 1, 2000), (1, 70, 1, 300000)):
+            _cmp(cb.cuboid_sieve_range(ctx, *rect, primes, cap=1 << 16), oracle.sieve(*rect, primes))
+        rects = wl.random_rectangles(30, seed=91, max_coord=50000, max_side=700)
+        st, out = cb.cuboid_sieve_batch(ctx, rects, primes, caps=4096)
+        assert st == cb.OK
+        for rect, r in zip(rects, out):
+            _cmp(r, oracle.sieve(*rect, primes))
+    finally:
+        cb.cuboid_set_tuning(ctx, primes)
