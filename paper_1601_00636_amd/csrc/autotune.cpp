@@ -100,16 +100,19 @@ int tune(cuboid_ctx *ctx, const std::vector<uint32_t> &sorted, const cuboid_requ
     double best_ms = 1e30;
     best.dense_primes = 0; best.workgroups = cus; best.lds_budget = budget; best.schedule = 0;
     best.piece_units = 0;
-    // the best sweep time of three runs under tuning t
+    // the median sweep time of five runs under tuning t (a best-of-few
+    // would favour tunings whose time varies most from run to run)
     auto time_of = [&](const cuboid_tuning &t, double *ms) -> int {
         ctx->tunings[sorted] = t;
-        *ms = 1e30;
-        for (int rep = 0; rep < 3; ++rep) {
+        double v[5];
+        for (int rep = 0; rep < 5; ++rep) {
             int r = sieve_rects(ctx, sorted, sample, n_sample, 1 << 16, ctx->stream, &ctx->h_out);
             if (r == CUBOID_E_LIMIT || r == CUBOID_E_CAPACITY) r = CUBOID_OK;
             if (r) return r;
-            *ms = std::min(*ms, ctx->last.sweep_ms);
+            v[rep] = ctx->last.sweep_ms;
         }
+        std::sort(v, v + 5);
+        *ms = v[2];
         return CUBOID_OK;
     };
     const uint32_t klo = kmax > 5 ? kmax - 5 : 0;
