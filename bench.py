@@ -224,11 +224,11 @@ def host_cpu():
     return info
 
 
-def cpu_full():
+def cpu_squares(c3_stride=32, log=True):
     """The CPU-baseline plan of the three plain squares: the oracle (tables
     built first and excluded) on [1, 200]^2 / 3..31, [1, 1e4]^2 / 3..97 and
     [1, 1e5]^2 / 3..997 in full on all host threads, and on one thread (the
-    largest square on one thread over every 32nd row, scaled, as a full run
+    largest square on one thread over every c3_stride-th row, as a full run
     would take about ten minutes)."""
     import oracle
     from paper_1601_00636_amd import workloads as wl
@@ -252,17 +252,22 @@ def cpu_full():
         else:
             t = time.time()
             n1 = 0
-            for row in range(p0, p1 + 1, 32):
+            for row in range(p0, p1 + 1, c3_stride):
                 n1 += oracle.sieve(row, row, q0, q1, primes, cap=1 << 16, threads=1)["n_pairs"]
             d1 = time.time() - t
             one = {"seconds": d1, "pairs_per_s": n1 / d1,
-                   "sample": "every 32nd row (%d coprime pairs)" % n1}
+                   "sample": "every %dth row (%d coprime pairs)" % (c3_stride, n1)}
         out["runs"][name] = {"n_pairs": int(res["n_pairs"]), "survivors": int(res["n_survivors"]),
                              "tables_seconds": t_tab, "all_threads": {"threads": threads,
                              "seconds": dt, "pairs_per_s": res["n_pairs"] / dt},
                              "one_thread": one}
-        print(name, json.dumps(out["runs"][name]), file=sys.stderr, flush=True)
-    print(json.dumps(out))
+        if log:
+            print(name, json.dumps(out["runs"][name]), file=sys.stderr, flush=True)
+    return out
+
+
+def cpu_full():
+    print(json.dumps(cpu_squares()))
     return 0
 
 
@@ -676,6 +681,10 @@ def main():
 
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = run_cpu_baseline(reqs, primes, args.cpu_stride)
+        # the three plain squares in full (the largest on one thread over
+        # every 64th row)
+        sq = cpu_squares(c3_stride=64)
+        res["cpu_baseline"]["squares"] = sq["runs"]
     dev.free()
     cb.cuboid_destroy(ctx)
     print(json.dumps(res))

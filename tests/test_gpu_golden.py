@@ -91,6 +91,29 @@ def test_all_4096_requests_host_results(ctx):
             [int(x) for x in g["survivors"][off[i]:off[i + 1]]]
 
 
+def test_all_4096_requests_served(ctx):
+    # the same 4096 rectangles submitted to the request server at once
+    # (continuous batching over its launches and streams)
+    g = _c4()
+    reqs = wl.batched_requests(4096)
+    primes = [int(r) for r in g["primes"]]
+    off = g["survivor_offsets"].astype(np.int64)
+    _say("c4 all 4096 requests through the server")
+    srv = cb.cuboid_server_start(ctx, primes, streams=2)
+    try:
+        tickets = [cb.cuboid_server_submit(srv, r) for r in reqs]
+        got = [cb.cuboid_server_poll(srv, t, len(primes), cap=64) for t in tickets]
+        stats = cb.cuboid_server_stats_get(srv)
+    finally:
+        cb.cuboid_server_stop(srv)
+    assert stats["completed"] == len(reqs) and stats["max_admitted"] > 1
+    for i, r in enumerate(got):
+        assert r["status"] == cb.OK
+        assert r["n_pairs"] == int(g["n_pairs"][i])
+        assert np.array_equal(np.asarray(r["counts"], dtype=np.uint64), g["counts"][i])
+        assert [int(x) for x in r["survivors"]] == [int(x) for x in g["survivors"][off[i]:off[i + 1]]]
+
+
 def _row_rmax(row, primes):
     if row["n_pairs"] == 0:
         return 1

@@ -3,6 +3,7 @@
 Bit-exact for everything (integer work): unsolvability tables byte for byte,
 n_pairs, per-prime counts and sorted survivor lists, root lists.
 """
+import functools
 import json
 import os
 import sys
@@ -333,6 +334,42 @@ def test_batch_capacity_per_request(ctx):
     _cmp(out[0], oracle.sieve(1, 200, 1, 200, wl.PRIMES_C1))
 
 
+def _coprime_pairs_square(n):
+    """Ordered coprime pairs p != q in [1, n]^2: 2 (phi(1) + ... + phi(n)) - 2
+    (the diagonal holds only (1, 1))."""
+    phi = np.arange(n + 1, dtype=np.int64)
+    for k in range(2, n + 1):
+        if phi[k] == k:
+            phi[k::k] -= phi[k::k] // k
+    return 2 * int(phi[1:].sum()) - 2
+
+
+def test_survivors_beyond_the_device_list(ctx):
+    # only trivial primes, so every coprime pair survives: 6.83e7 of them are
+    # more than the 2^26 survivors a call keeps on the device, so the call
+    # returns E_LIMIT and each request its survivor count (pairs minus the
+    # counts) without a list
+    n = 10600
+    want = _coprime_pairs_square(n)
+    assert want > 1 << 26
+    primes = [3, 5, 7]
+    st, out = cb.cuboid_sieve_batch(ctx, [(1, n, 1, n), (1, 30, 1, 30)], primes, caps=16)
+    assert st == cb.E_LIMIT
+    assert out[0]["n_pairs"] == want and out[0]["n_survivors"] == want
+    assert out[0]["status"] == cb.E_CAPACITY
+    assert out[1]["n_pairs"] == out[1]["n_survivors"] == _coprime_pairs_square(30)
+    assert out[1]["status"] == cb.E_CAPACITY
+    assert [int(c) for c in out[0]["counts"]] == [0, 0, 0]
+    dev = cb.DeviceBatch(ctx, 1, len(primes), surv_cap=16)
+    try:
+        assert cb.cuboid_sieve_batch_dev(ctx, [(1, n, 1, n)], primes, dev) == cb.E_LIMIT
+        assert dev.n_survivors == want
+        counts, pairs, _ = dev.read()
+        assert int(pairs[0]) == want and int(counts.sum()) == 0
+    finally:
+        dev.free()
+
+
 @pytest.mark.parametrize("tuned", [False, True])
 def test_c4_sample_against_oracle(ctx, tuned):
     # the full 4096-rectangle batch, with the default tuning and with the one
@@ -395,16 +432,21 @@ def test_workgroup_pieces_large_and_odd_grids(ctx, wg):
     # pieces per wave on the full grid.
     primes = wl.PRIMES_C2
     rect = (1, 8200, 1, 70000)
+    ref = _oracle_large_rect()
     cb.cuboid_set_tuning(ctx, primes, schedule=1)
     try:
-        ref = cb.cuboid_sieve_range(ctx, *rect, primes, cap=1 << 16)
+        _cmp(cb.cuboid_sieve_range(ctx, *rect, primes, cap=1 << 16), ref)
         cb.cuboid_set_tuning(ctx, primes, schedule=3, workgroups=wg)
         got = cb.cuboid_sieve_range(ctx, *rect, primes, cap=1 << 16)
     finally:
         cb.cuboid_set_tuning(ctx, primes)
-    assert got["n_pairs"] == ref["n_pairs"] > 0
-    assert [int(c) for c in got["counts"]] == [int(c) for c in ref["counts"]]
-    assert [int(x) for x in got["survivors"]] == [int(x) for x in ref["survivors"]]
+    assert ref["n_pairs"] > 0
+    _cmp(got, ref)
+
+
+@functools.lru_cache(maxsize=1)
+def _oracle_large_rect():
+    return oracle.sieve(1, 8200, 1, 70000, wl.PRIMES_C2, cap=1 << 16)
 
 
 def test_schedule_out_of_range(ctx):

@@ -2,7 +2,9 @@
 section 6 against the paper's printed result, rows beyond the resident table
 against per-row rectangles.
 """
+import functools
 import json
+import os
 
 import numpy as np
 import pytest
@@ -159,27 +161,80 @@ def test_section6_scan_against_the_oracle(ctx):
     assert g["max_depth_prime"] == 137
 
 
+@functools.lru_cache(maxsize=1)
+def _oracle_rows_1_4000():
+    ref = oracle.sieve_region(1, 4000, wl.PRIMES_PAPER)
+    return ref, _section6_rmax(40) or _oracle_band_rmax(1, 4000, 100, wl.PRIMES_PAPER)
+
+
+def _section6_rmax(n_bands):
+    """r_max of the first bands of 100 rows from the oracle's run of the
+    section 6 scan, or None if that file is absent."""
+    path = golden_path("oracle_s6.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        g = json.load(f)
+    assert g["band_rows"] == 100 and g["primes"] == sorted(wl.PRIMES_PAPER)
+    return g["r_max"][:n_bands]
+
+
+def _region_pairs(p0, p1):
+    """Coprime pairs p != q of region (1.2) in rows p0..p1, counted for each
+    row by inclusion-exclusion over the prime factors of p."""
+    total = 0
+    for p in range(p0, p1 + 1):
+        lo, hi = oracle.region_qmin(p), 59 * p
+        fac, x, d = [], p, 2
+        while d * d <= x:
+            if x % d == 0:
+                fac.append(d)
+                while x % d == 0:
+                    x //= d
+            d += 1
+        if x > 1:
+            fac.append(x)
+        n = 0
+        for mask in range(1 << len(fac)):
+            m, sign = 1, 1
+            for k, f in enumerate(fac):
+                if mask >> k & 1:
+                    m, sign = m * f, -sign
+            n += sign * (hi // m - (lo - 1) // m)
+        total += n - (1 if p == 1 and lo <= 1 else 0)
+    return total
+
+
+def test_region_pair_count_formula():
+    # the counting formula above against the oracle on a slice
+    ref = oracle.sieve_region(1, 300, wl.PRIMES_PAPER)
+    assert _region_pairs(1, 300) == ref["n_pairs"]
+
+
 @pytest.mark.parametrize("schedule", [1, 2, 3])
 def test_region_under_each_work_schedule(ctx, schedule):
     # the region scan of rows 1..4000 with primes 11..541 under each way of
-    # sharing units between waves, against the default
+    # sharing units between waves, against the oracle
     primes = wl.PRIMES_PAPER
-    ref = cb.cuboid_sieve_region(ctx, 1, 4000, primes, band_rows=100)
+    ref, rmax = _oracle_rows_1_4000()
     cb.cuboid_set_tuning(ctx, primes, schedule=schedule, workgroups=5)
     try:
         got = cb.cuboid_sieve_region(ctx, 1, 4000, primes, band_rows=100)
     finally:
         cb.cuboid_set_tuning(ctx, primes)
+    asc = sorted(primes)
+    by_prime = dict(zip(asc, [int(c) for c in ref["counts"]]))
     assert got["n_pairs"] == ref["n_pairs"]
-    assert [int(c) for c in got["counts"]] == [int(c) for c in ref["counts"]]
+    assert [int(c) for c in got["counts"]] == [by_prime[r] for r in primes]
     assert got["survivors"] == ref["survivors"]
-    assert [int(x) for x in got["r_max"]] == [int(x) for x in ref["r_max"]]
+    assert [int(x) for x in got["r_max"]] == rmax
 
 
 def test_region_large_workgroup_pieces(ctx):
     # rows 1..20000 on a grid of one workgroup: over 32 * 4096 units, so the
     # workgroup's share comes in pieces of 4096 units; against round-robin
-    # pieces per wave on the full grid
+    # pieces per wave on the full grid, the pair count by inclusion-exclusion
+    # and the oracle's r_max of each hundred rows
     primes = wl.PRIMES_PAPER
     cb.cuboid_set_tuning(ctx, primes, schedule=1)
     try:
@@ -189,7 +244,10 @@ def test_region_large_workgroup_pieces(ctx):
     finally:
         cb.cuboid_set_tuning(ctx, primes)
     assert ref["n_pairs"] > 32 * 4096 * 4096 // 2
-    assert got["n_pairs"] == ref["n_pairs"]
+    assert got["n_pairs"] == ref["n_pairs"] == _region_pairs(1, 20000)
     assert [int(c) for c in got["counts"]] == [int(c) for c in ref["counts"]]
-    assert got["survivors"] == ref["survivors"]
+    assert got["survivors"] == ref["survivors"] == []
     assert [int(x) for x in got["r_max"]] == [int(x) for x in ref["r_max"]]
+    rmax = _section6_rmax(200)
+    if rmax is not None:
+        assert [int(x) for x in got["r_max"]] == rmax
