@@ -185,8 +185,8 @@ hipError_t launch_sort_surv(SurvEntry *a, SurvEntry *tmp, const unsigned long lo
                             uint64_t cap, SurvEntry **out, hipStream_t s);
 // Replica sums, counts in the caller's order (col, or canonical when null) and
 // the survivor count n, in one launch: out_counts[n_slots][np],
-// out_pairs[n_slots], *out_n; with small_cap (<= kSmallSort) also the first
-// min(n, small_cap) survivors of surv, sorted, into out_surv.
+// out_pairs[n_slots], *out_n; with small_cap (<= kSmallSort) and
+// n <= small_cap also the n survivors of surv, sorted, into out_surv.
 constexpr uint64_t kSmallSort = 1024;
 hipError_t launch_finish(const unsigned long long *counts, const unsigned long long *pairs,
                          uint32_t n_rep, uint64_t stride_c, uint64_t stride_p, const int32_t *col,

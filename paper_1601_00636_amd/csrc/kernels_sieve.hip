@@ -612,8 +612,7 @@ __global__ void __launch_bounds__(256) block_sort_kernel(SurvEntry *a, const uns
 // the n_rep replicas of counter col[j] of the slot (0 where col[j] < 0; the
 // canonical counters, j itself, when col is null), out_pairs[slot] = the sum
 // of the pair-count replicas, *out_n = the survivor count n; with small_cap
-// > 0 block 0 also sorts the first min(n, small_cap) survivors into out_surv
-// (all of them when n <= small_cap).
+// > 0 and n <= small_cap block 0 also sorts the n survivors into out_surv.
 __global__ void __launch_bounds__(256) finish_kernel(
     const unsigned long long *counts, const unsigned long long *pairs, uint32_t n_rep,
     uint64_t stride_c, uint64_t stride_p, const int32_t *col, uint32_t n_slots, uint32_t nc,
@@ -646,9 +645,13 @@ __global__ void __launch_bounds__(256) finish_kernel(
     }
     if (blockIdx.x != 0 || small_cap == 0) return;
     __shared__ SurvEntry sv[kSortTile];
-    const uint64_t m = *surv_n < small_cap ? *surv_n : small_cap;
-    if (m == 0) return;
-    for (uint32_t i = threadIdx.x; i < (uint32_t)kSortTile; i += blockDim.x) {
+    // (more than small_cap survivors are sorted by the caller's own passes)
+    const uint64_t m = *surv_n;
+    if (m == 0 || m > small_cap) return;
+    // bitonic sort over the least power of two >= m (at most kSortTile)
+    uint32_t n2 = 2;
+    while (n2 < m) n2 <<= 1;
+    for (uint32_t i = threadIdx.x; i < n2; i += blockDim.x) {
         if (i < m) {
             sv[i] = surv[i];
         } else {
@@ -656,9 +659,9 @@ __global__ void __launch_bounds__(256) finish_kernel(
         }
     }
     __syncthreads();
-    for (uint32_t k = 2; k <= (uint32_t)kSortTile; k <<= 1) {
+    for (uint32_t k = 2; k <= n2; k <<= 1) {
         for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t i = threadIdx.x; i < (uint32_t)kSortTile; i += blockDim.x) {
+            for (uint32_t i = threadIdx.x; i < n2; i += blockDim.x) {
                 const uint32_t ixj = i ^ j;
                 if (ixj > i) {
                     const bool up = (i & k) == 0;
