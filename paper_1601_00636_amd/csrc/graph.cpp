@@ -13,9 +13,9 @@
 // context (least recently used out) and keyed by every pointer and size they
 // bake in.
 //
-// With per-call timing on the graph is a parent of three captured parts
-// (before / sweep / after) so that event-record nodes can bracket the sweep;
-// otherwise it is one flat capture, which is cheaper to launch.
+// The graph is one flat capture (a parent of captured parts costs more to
+// launch); with per-call timing on, event-record nodes are then added on
+// both sides of the sweep node.
 // Clears are fill kernels: no memset nodes.
 #include <string.h>
 
@@ -70,6 +70,45 @@ hipError_t capture_part(hipStream_t s, hipGraph_t *g, F record) {
     return hipSuccess;
 }
 
+// With per-call timing: the captured graph is a chain (upload, clear, the
+// regrouping when present, sweep, finishing kernel, download); put an
+// event-record node on each side of the sweep, its node number `at` from 0.
+hipError_t bracket_sweep(cuboid_ctx *ctx, hipGraph_t g, size_t at) {
+    std::vector<hipGraphNode_t> chain;
+    size_t n = 1;
+    hipGraphNode_t node = nullptr;
+    hipError_t e = hipGraphGetRootNodes(g, &node, &n);
+    if (e != hipSuccess) return e;
+    if (n != 1) return hipErrorInvalidValue;
+    while (node) {
+        chain.push_back(node);
+        size_t nd = 0;
+        e = hipGraphNodeGetDependentNodes(node, nullptr, &nd);
+        if (e != hipSuccess) return e;
+        if (nd > 1) return hipErrorInvalidValue;
+        hipGraphNode_t next = nullptr;
+        if (nd == 1) {
+            e = hipGraphNodeGetDependentNodes(node, &next, &nd);
+            if (e != hipSuccess) return e;
+        }
+        node = next;
+    }
+    if (at == 0 || at + 1 >= chain.size()) return hipErrorInvalidValue;
+    hipGraphNodeType type;
+    e = hipGraphNodeGetType(chain[at], &type);
+    if (e != hipSuccess) return e;
+    if (type != hipGraphNodeTypeKernel) return hipErrorInvalidValue;
+    hipGraphNode_t before = chain[at - 1], sweep = chain[at], after = chain[at + 1];
+    hipGraphNode_t ev0 = nullptr, ev1 = nullptr;
+    e = hipGraphRemoveDependencies(g, &before, &sweep, 1);
+    if (e == hipSuccess) e = hipGraphAddEventRecordNode(&ev0, g, &before, 1, ctx->ev_sweep0);
+    if (e == hipSuccess) e = hipGraphAddDependencies(g, &ev0, &sweep, 1);
+    if (e == hipSuccess) e = hipGraphRemoveDependencies(g, &sweep, &after, 1);
+    if (e == hipSuccess) e = hipGraphAddEventRecordNode(&ev1, g, &sweep, 1, ctx->ev_sweep1);
+    if (e == hipSuccess) e = hipGraphAddDependencies(g, &ev1, &after, 1);
+    return e;
+}
+
 struct GraphArgs {
     SweepParams P;
     unsigned char *block;
@@ -92,7 +131,7 @@ hipError_t build_graph(cuboid_ctx *ctx, const GraphArgs &a, hipStream_t s, Batch
     const uint32_t n = a.n, ns = a.n_slots, nc = a.nc;
     const uint64_t ncount = (uint64_t)ns * nc;
     const uint64_t nout = (uint64_t)ns * (a.gather ? a.np : nc);
-    hipGraph_t pre = nullptr, sweep = nullptr, post = nullptr, parent = nullptr;
+    hipGraph_t parent = nullptr;
     hipGraphExec_t exec = nullptr;
     auto record_pre = [&]() -> hipError_t {
         hipError_t r = hipMemcpyAsync(a.block, a.stage, a.L.bytes, hipMemcpyHostToDevice, s);
@@ -109,66 +148,45 @@ hipError_t build_graph(cuboid_ctx *ctx, const GraphArgs &a, hipStream_t s, Batch
     };
     auto record_sweep = [&]() { return launch_sweep(a.P, (int)a.grid, a.lds, a.max_p, s); };
     auto record_post = [&]() -> hipError_t {
-            // output block (device, downloaded whole into the result staging):
-            // [nout counts | ns pairs | survivor count | small_sort survivors];
-            // with device destinations only the survivor count is in it
-            unsigned long long *ob = (unsigned long long *)ctx->gathered.p;
-            unsigned long long *oc = a.dcounts ? (unsigned long long *)a.dcounts : ob;
-            unsigned long long *op = a.dpairs ? (unsigned long long *)a.dpairs : ob + nout;
-            unsigned long long *on = a.dcounts ? ob : ob + nout + ns;
-            hipError_t r = launch_finish((const unsigned long long *)ctx->counts.p,
-                                         (const unsigned long long *)ctx->pairs.p, ctx->n_rep,
-                                         ctx->rep_stride_counts, ctx->rep_stride_pairs,
-                                         a.gather ? (const int32_t *)(a.block + a.L.o_col) : nullptr,
-                                         ns, nc, a.gather ? a.np : nc, oc, op,
-                                         (const unsigned long long *)ctx->surv_n.p, on,
-                                         (const SurvEntry *)ctx->surv.p, a.small_sort,
-                                         (SurvEntry *)(on + 1), s);
-            if (r == hipSuccess && a.dcounts)
-                r = hipMemcpyAsync(a.result + nout + ns, on, 8, hipMemcpyDeviceToHost, s);
-            else if (r == hipSuccess)
-                r = hipMemcpyAsync(a.result, ob, (nout + ns + 1 + 2 * a.small_sort) * 8,
-                                   hipMemcpyDeviceToHost, s);
-            return r;
-        };
-    hipError_t e = hipSuccess;
-    if (!a.timing) {
-        // one flat capture (a nested graph costs more to launch)
-        e = capture_part(s, &parent, [&]() -> hipError_t {
-            hipError_t r = record_pre();
-            if (r == hipSuccess) r = record_sweep();
-            if (r == hipSuccess) r = record_post();
-            return r;
-        });
-    } else {
-        // three captured parts with event-record nodes around the sweep
-        e = capture_part(s, &pre, record_pre);
-        if (e == hipSuccess) e = capture_part(s, &sweep, record_sweep);
-        if (e == hipSuccess) e = capture_part(s, &post, record_post);
-        if (e == hipSuccess) e = hipGraphCreate(&parent, 0);
-    }
+        // output block (device, downloaded whole into the result staging):
+        // [nout counts | ns pairs | survivor count | small_sort survivors];
+        // with device destinations only the survivor count is in it
+        unsigned long long *ob = (unsigned long long *)ctx->gathered.p;
+        unsigned long long *oc = a.dcounts ? (unsigned long long *)a.dcounts : ob;
+        unsigned long long *op = a.dpairs ? (unsigned long long *)a.dpairs : ob + nout;
+        unsigned long long *on = a.dcounts ? ob : ob + nout + ns;
+        hipError_t r = launch_finish((const unsigned long long *)ctx->counts.p,
+                                     (const unsigned long long *)ctx->pairs.p, ctx->n_rep,
+                                     ctx->rep_stride_counts, ctx->rep_stride_pairs,
+                                     a.gather ? (const int32_t *)(a.block + a.L.o_col) : nullptr,
+                                     ns, nc, a.gather ? a.np : nc, oc, op,
+                                     (const unsigned long long *)ctx->surv_n.p, on,
+                                     (const SurvEntry *)ctx->surv.p, a.small_sort,
+                                     (SurvEntry *)(on + 1), s);
+        if (r == hipSuccess && a.dcounts)
+            r = hipMemcpyAsync(a.result + nout + ns, on, 8, hipMemcpyDeviceToHost, s);
+        else if (r == hipSuccess)
+            r = hipMemcpyAsync(a.result, ob, (nout + ns + 1 + 2 * a.small_sort) * 8,
+                               hipMemcpyDeviceToHost, s);
+        return r;
+    };
+    // one flat capture (a nested graph costs more to launch)
+    hipError_t e = capture_part(s, &parent, [&]() -> hipError_t {
+        hipError_t r = record_pre();
+        if (r == hipSuccess) r = record_sweep();
+        if (r == hipSuccess) r = record_post();
+        return r;
+    });
     if (e == hipSuccess && a.timing) {
-        hipGraphNode_t prev = nullptr, node = nullptr;
-        e = hipGraphAddChildGraphNode(&node, parent, nullptr, 0, pre);
-        prev = node;
-        if (e == hipSuccess) {
-            e = hipGraphAddEventRecordNode(&node, parent, &prev, 1, ctx->ev_sweep0);
-            prev = node;
-        }
-        if (e == hipSuccess) {
-            e = hipGraphAddChildGraphNode(&node, parent, &prev, 1, sweep);
-            prev = node;
-        }
-        if (e == hipSuccess) {
-            e = hipGraphAddEventRecordNode(&node, parent, &prev, 1, ctx->ev_sweep1);
-            prev = node;
-        }
-        if (e == hipSuccess) e = hipGraphAddChildGraphNode(&node, parent, &prev, 1, post);
+        // the sweep's place in the chain: the node count of the part before it
+        hipGraph_t pre = nullptr;
+        size_t n_pre = 0;
+        e = capture_part(s, &pre, record_pre);
+        if (e == hipSuccess) e = hipGraphGetNodes(pre, nullptr, &n_pre);
+        if (pre) (void)hipGraphDestroy(pre);
+        if (e == hipSuccess) e = bracket_sweep(ctx, parent, n_pre);
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&exec, parent, nullptr, nullptr, 0);
-    if (pre) (void)hipGraphDestroy(pre);
-    if (sweep) (void)hipGraphDestroy(sweep);
-    if (post) (void)hipGraphDestroy(post);
     if (e != hipSuccess) {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (parent) (void)hipGraphDestroy(parent);
