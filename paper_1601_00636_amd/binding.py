@@ -19,7 +19,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libcuboid.so")
+# CUBOID_LIB selects another build of the library (e.g. the host-sanitized one)
+LIB_PATH = os.environ.get("CUBOID_LIB") or os.path.join(_HERE, "libcuboid.so")
 
 (OK, E_BUSY, E_RANGE, E_LIMIT, E_PRIMES, E_CAPACITY, E_NOT_LOADED, E_DEVICE, E_ARG, E_IO,
  E_DATA) = range(11)

@@ -1,6 +1,10 @@
 """Builds libcuboid.so (HIP for gfx950) next to this file.
 
 usage: python -m paper_1601_00636_amd.build   (or build() from Python)
+       python -m paper_1601_00636_amd.build --host-sanitize
+           also builds _build_san/libcuboid.so, whose host C++ runs under
+           AddressSanitizer and UBSan (device code as usual); load it with
+           CUBOID_LIB=<that path> and gcc's libasan and libubsan in LD_PRELOAD
 """
 import os
 import subprocess
@@ -41,15 +45,21 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def _compile(src):
-    obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
+# host C++ instrumentation of the sanitized build (gcc's runtimes)
+SANITIZE = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-g"]
+SAN_DIR = os.path.join(HERE, "_build_san")
+
+
+def _compile(src, build_dir=BUILD_DIR, sanitize=False):
+    obj = os.path.join(build_dir, os.path.basename(src) + ".o")
     path = os.path.join(CSRC, src)
     if src.endswith(".hip"):
         cmd = [HIPCC] + DEVICE + COMMON + ["-x", "hip", "-c", path, "-o", obj]
     else:
         # host-only C++ (HIP runtime API through its headers)
-        cmd = [CXX] + COMMON + ["-D__HIP_PLATFORM_AMD__", "-I" + ROCM + "/include", "-pthread",
-                                "-c", path, "-o", obj]
+        extra = SANITIZE if sanitize else []
+        cmd = [CXX] + COMMON + extra + ["-D__HIP_PLATFORM_AMD__", "-I" + ROCM + "/include",
+                                        "-pthread", "-c", path, "-o", obj]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s" % (" ".join(cmd), r.stdout))
@@ -72,6 +82,26 @@ def build(verbose=False):
     return LIB
 
 
+def build_host_sanitized(verbose=False):
+    """libcuboid.so with AddressSanitizer and UBSan in its host C++, in _build_san/."""
+    os.makedirs(SAN_DIR, exist_ok=True)
+    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+        objs = list(ex.map(lambda f: _compile(f, SAN_DIR, True), SOURCES))
+    runtimes = [subprocess.run([CXX, "-print-file-name=" + n], stdout=subprocess.PIPE,
+                               text=True).stdout.strip() for n in ("libasan.so", "libubsan.so")]
+    lib = os.path.join(SAN_DIR, "libcuboid.so")
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", lib] + objs + runtimes + \
+        ["-lpthread"]
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed: %s\n%s" % (" ".join(cmd), r.stdout))
+    if verbose:
+        print("built", lib, "(preload:", " ".join(runtimes) + ")")
+    return lib
+
+
 if __name__ == "__main__":
     build(verbose=True)
+    if "--host-sanitize" in sys.argv[1:]:
+        build_host_sanitized(verbose=True)
     sys.exit(0)
