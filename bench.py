@@ -288,25 +288,44 @@ def calibrate_copy():
     return 0
 
 
+def replay_to_server(cb, srv, stream, n_primes, cap):
+    """Submit a timed stream [(arrival s, rect)] to a server as it arrives: each
+    pass of the host loop queues every request already due in one call, so the
+    offered rate is not limited by one call per request.  Returns the results
+    and each request's latency from its arrival (server completion stamps and
+    this loop use the same monotonic clock)."""
+    ats = [int(at * 1e9) for at, _ in stream]
+    rects = [r for _, r in stream]
+    n = len(rects)
+    tickets = []
+    t0 = time.monotonic_ns()
+    i = 0
+    while i < n:
+        now = time.monotonic_ns() - t0
+        j = i
+        while j < n and ats[j] <= now:
+            j += 1
+        if j > i:
+            tickets.extend(int(t) for t in cb.cuboid_server_submit_many(srv, rects[i:j]))
+            i = j
+    t_sub = (time.monotonic_ns() - t0) / 1e9
+    out = [cb.cuboid_server_poll(srv, t, n_primes, cap=cap) for t in tickets]
+    lat_ms = np.array([x["done_ns"] - (t0 + a) for x, a in zip(out, ats)], dtype=np.float64) / 1e6
+    span = (max(x["done_ns"] for x in out) - (t0 + ats[0])) / 1e9
+    return out, lat_ms, span, t_sub
+
+
 def run_served(cb, wl, ctx, primes, seconds):
     """Replay the seeded Poisson stream (2000 requests/s, areas log-uniform in
-    [1e3, 1e9]) against the server; latency = completion - submission."""
+    [1e3, 1e9]) against the server; latency = completion - arrival."""
     stream = wl.served_stream(duration=seconds, max_requests=int(2000 * seconds))
     srv = cb.cuboid_server_start(ctx, primes)
     try:
-        t0 = time.perf_counter()
-        tickets = []
-        for at, rect in stream:
-            while time.perf_counter() - t0 < at:
-                pass
-            tickets.append(cb.cuboid_server_submit(srv, rect))
-        out = [cb.cuboid_server_poll(srv, t, len(primes), cap=4096) for t in tickets]
+        out, lat, span, _ = replay_to_server(cb, srv, stream, len(primes), 4096)
         stats = cb.cuboid_server_stats_get(srv)
     finally:
         cb.cuboid_server_stop(srv)
-    lat = np.array([r["latency_ns"] for r in out], dtype=np.float64) / 1e6
     pairs = sum(r["n_pairs"] for r in out)
-    span = (max(r["done_ns"] for r in out) - min(r["submit_ns"] for r in out)) / 1e9
     return {"requests": len(out), "offered_rate_per_s": 2000, "seconds": seconds,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "max_ms": float(lat.max()), "coprime_pairs": pairs,
@@ -316,37 +335,36 @@ def run_served(cb, wl, ctx, primes, seconds):
 
 def run_served_vs_plain(cb, wl, ctx, primes, rates=(2000, 20000, 200000), n_req=3000):
     """The same seeded Poisson streams (areas log-uniform in [1e3, 1e9]) at
-    several offered rates, once through the server (continuous batching) and
-    once as one plain cuboid_sieve_range call per request from one thread in
-    arrival order; latency = completion - arrival (for the server: completion
-    - submission, stamped by the server)."""
+    several offered rates and as a burst, once through the server (continuous
+    batching; due requests queued together) and once as one plain
+    cuboid_sieve_range call per request from one thread in arrival order;
+    latency = completion - arrival for both."""
     out = {}
     for rate in list(rates) + ["burst"]:
         r = 1e9 if rate == "burst" else float(rate)
         stream = wl.served_stream(rate=r, duration=1e9, max_requests=n_req)
         if rate == "burst":
             stream = [(0.0, rect) for _, rect in stream]
-        # served
-        srv = cb.cuboid_server_start(ctx, primes)
-        try:
-            t0 = time.perf_counter()
-            tickets = []
-            for at, rect in stream:
-                while time.perf_counter() - t0 < at:
-                    pass
-                tickets.append(cb.cuboid_server_submit(srv, rect))
-            t_sub = time.perf_counter() - t0
-            res = [cb.cuboid_server_poll(srv, t, len(primes), cap=1 << 14) for t in tickets]
-            stats = cb.cuboid_server_stats_get(srv)
-        finally:
-            cb.cuboid_server_stop(srv)
-        lat = np.array([x["latency_ns"] for x in res], dtype=np.float64) / 1e6
+        # served: three replays, each on a fresh server; the one with the
+        # median throughput is reported
+        runs = []
+        for _ in range(3):
+            srv = cb.cuboid_server_start(ctx, primes)
+            try:
+                res, lat, span, t_sub = replay_to_server(cb, srv, stream, len(primes), 1 << 14)
+                stats = cb.cuboid_server_stats_get(srv)
+            finally:
+                cb.cuboid_server_stop(srv)
+            pairs = sum(x["n_pairs"] for x in res)
+            runs.append((pairs / span, res, lat, span, t_sub, stats))
+        runs.sort(key=lambda x: x[0])
+        _, res, lat, span, t_sub, stats = runs[1]
         pairs = sum(x["n_pairs"] for x in res)
-        span = (max(x["done_ns"] for x in res) - min(x["submit_ns"] for x in res)) / 1e9
         served = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                   "pairs_per_s": pairs / span, "span_s": span,
                   "submitted_per_s": len(res) / t_sub if t_sub > 0 else None,
-                  "launches": stats["launches"], "max_admitted": stats["max_admitted"]}
+                  "launches": stats["launches"], "max_admitted": stats["max_admitted"],
+                  "pairs_per_s_of_the_three": [x[0] for x in runs]}
         # plain, one call per request in arrival order
         lat_p = []
         pairs_p = 0

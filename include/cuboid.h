@@ -351,7 +351,7 @@ typedef struct cuboid_server cuboid_server;
 typedef struct cuboid_server_config {
     uint32_t streams;             /* launches in flight at once (0 = 2)                  */
     uint32_t max_slots;           /* requests admitted at once (0 = 4096)                */
-    uint64_t max_launch_units;    /* units per launch (0 = 2^20)                         */
+    uint64_t max_launch_units;    /* units per launch (0 = 2^22)                         */
     uint64_t hbm_budget_bytes;    /* device memory for per-request row orders; 0 = a      */
                                   /* quarter of the free device memory, 64 MiB .. 4 GiB   */
 } cuboid_server_config;
@@ -382,6 +382,16 @@ int cuboid_server_start(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_prim
  * case).  Errors: E_RANGE (invalid rectangle), E_BUSY (stopping).
  */
 int cuboid_server_submit(cuboid_server *srv, const cuboid_request *req, uint64_t *ticket);
+
+/*
+ * Queue n rectangles at once (one lock, one wake-up of the server), as n
+ * calls of cuboid_server_submit would: tickets[i] identifies req[i].  All or
+ * none are queued: an invalid rectangle queues none and returns E_RANGE with
+ * *bad set to its index (bad may be NULL).  Errors: E_ARG (n = 0 or a null
+ * pointer), E_RANGE, E_BUSY (stopping).
+ */
+int cuboid_server_submit_many(cuboid_server *srv, const cuboid_request *req, uint32_t n,
+                              uint64_t *tickets, uint32_t *bad);
 
 /*
  * Results of a ticket into res (counts[n_primes], survivors up to res->cap,

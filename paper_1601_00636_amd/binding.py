@@ -160,6 +160,7 @@ def _load():
         "cuboid_search_stop": ([vp, P(cuboid_search_report)], i32),
         "cuboid_server_start": ([vp, P(u32), u32, P(cuboid_server_config), P(vp)], i32),
         "cuboid_server_submit": ([vp, P(cuboid_request), P(u64)], i32),
+        "cuboid_server_submit_many": ([vp, P(cuboid_request), u32, P(u64), P(u32)], i32),
         "cuboid_server_poll": ([vp, u64, P(cuboid_result), i32, P(cuboid_request_timing)], i32),
         "cuboid_server_stats_get": ([vp, P(cuboid_server_stats)], i32),
         "cuboid_server_stop": ([vp], i32),
@@ -679,6 +680,19 @@ def cuboid_server_submit(srv, rect):
     _check(_load().cuboid_server_submit(srv, ctypes.byref(r), ctypes.byref(t)),
            "cuboid_server_submit")
     return t.value
+
+
+def cuboid_server_submit_many(srv, rects):
+    """Queue many rectangles in one call; returns their tickets (numpy uint64).
+    An invalid rectangle queues none: CuboidError E_RANGE, with .needed set to
+    its index."""
+    reqa = np.ascontiguousarray(np.asarray(rects, dtype=np.uint32).reshape(-1, 4))
+    tickets = np.zeros(max(1, reqa.shape[0]), dtype=np.uint64)
+    bad = ctypes.c_uint32(0)
+    st = _load().cuboid_server_submit_many(srv, reqa.ctypes.data_as(P(cuboid_request)),
+                                           reqa.shape[0], _p(tickets, u64), ctypes.byref(bad))
+    _check(st, "cuboid_server_submit_many", needed=bad.value if st == E_RANGE else None)
+    return tickets[:reqa.shape[0]]
 
 
 def cuboid_server_poll(srv, ticket, n_primes, cap=1024, wait=True):

@@ -556,7 +556,7 @@ int cuboid_server_start(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_prim
     if (c.streams == 0) c.streams = 2;
     if (c.streams > 8) return CUBOID_E_ARG;
     if (c.max_slots == 0) c.max_slots = 4096;
-    if (c.max_launch_units == 0) c.max_launch_units = 1u << 20;
+    if (c.max_launch_units == 0) c.max_launch_units = 1u << 22;
     CtxLock g(ctx);
     if (hipSetDevice(ctx->device) != hipSuccess) return CUBOID_E_DEVICE;
     if (c.hbm_budget_bytes == 0) {
@@ -593,6 +593,17 @@ int cuboid_server_start(cuboid_ctx *ctx, const uint32_t *primes, uint32_t n_prim
         SRVCHK(hipEventCreateWithFlags(&sst.ev, hipEventDisableTiming));
         SRVCHK(sst.surv.ensure(kSurvPool * sizeof(SurvEntry)));
         SRVCHK(sst.surv_n.ensure(16));   // survivor count, claim counter
+        // a launch covers at most max_slots requests: its staging and output
+        // buffers are sized for that now, so that no launch grows them (a
+        // device free synchronises the device, a pinned allocation takes
+        // milliseconds)
+        const size_t m = c.max_slots;
+        const size_t stage = 2 * m * sizeof(ReqDesc) + 2 * (m + 1) * 8 + 2 * m * 4 + 64;
+        const size_t fout = m * (S->nc + 1) * 8;
+        SRVCHK(sst.stage.ensure(stage));
+        SRVCHK(sst.reqbuf.ensure(stage));
+        SRVCHK(sst.out_dev.ensure(fout + 8));
+        SRVCHK(sst.out_host.ensure(fout + 8 + kSurvCopy * sizeof(SurvEntry)));
     }
     ctx->servers.fetch_add(1);
     cuboid_server *raw = S.release();
@@ -618,6 +629,36 @@ int cuboid_server_submit(cuboid_server *S, const cuboid_request *req, uint64_t *
     S->pending.push_back(t);
     S->stats.submitted++;
     *ticket = t;
+    S->cv_work.notify_one();
+    return CUBOID_OK;
+}
+
+int cuboid_server_submit_many(cuboid_server *S, const cuboid_request *req, uint32_t n,
+                              uint64_t *tickets, uint32_t *bad) {
+    if (!S || !req || !tickets || n == 0) return CUBOID_E_ARG;
+    for (uint32_t i = 0; i < n; ++i) {
+        const int st = rect_valid(req[i].p0, req[i].p1, req[i].q0, req[i].q1);
+        if (st) {
+            if (bad) *bad = i;
+            return st;
+        }
+    }
+    std::lock_guard<std::mutex> g(S->mu);
+    if (S->stopping) return CUBOID_E_BUSY;
+    const uint64_t t_now = now_ns();
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint64_t t = S->next_ticket++;
+        SrvReq &r = S->reqs[t];
+        r.rect = req[i];
+        const uint64_t rows = (uint64_t)req[i].p1 - req[i].p0 + 1;
+        r.nrb = (uint32_t)((rows + 63) / 64);
+        r.nwin = (uint32_t)(((uint64_t)req[i].q1 - req[i].q0 + 64) / 64);
+        r.units_total = (uint64_t)r.nrb * r.nwin;
+        r.t_submit = t_now;
+        S->pending.push_back(t);
+        tickets[i] = t;
+    }
+    S->stats.submitted += n;
     S->cv_work.notify_one();
     return CUBOID_OK;
 }

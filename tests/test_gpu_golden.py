@@ -92,7 +92,7 @@ def test_all_4096_requests_host_results(ctx):
 
 
 def test_all_4096_requests_served(ctx):
-    # the same 4096 rectangles submitted to the request server at once
+    # the same 4096 rectangles queued on the request server in one call
     # (continuous batching over its launches and streams)
     g = _c4()
     reqs = wl.batched_requests(4096)
@@ -101,8 +101,8 @@ def test_all_4096_requests_served(ctx):
     _say("c4 all 4096 requests through the server")
     srv = cb.cuboid_server_start(ctx, primes, streams=2)
     try:
-        tickets = [cb.cuboid_server_submit(srv, r) for r in reqs]
-        got = [cb.cuboid_server_poll(srv, t, len(primes), cap=64) for t in tickets]
+        tickets = cb.cuboid_server_submit_many(srv, reqs)
+        got = [cb.cuboid_server_poll(srv, int(t), len(primes), cap=64) for t in tickets]
         stats = cb.cuboid_server_stats_get(srv)
     finally:
         cb.cuboid_server_stop(srv)

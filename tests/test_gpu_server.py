@@ -132,6 +132,30 @@ def test_capacity_retry_and_errors(ctx):
         cb.cuboid_server_stop(srv)
 
 
+def test_submit_many(ctx):
+    # a batch of requests queued in one call gives the same results as one
+    # call per request; an invalid rectangle queues none of its batch
+    rects = _mix(7, 120) + [(1, 200, 1, 200), (9, 9, 1, 1)]
+    srv = cb.cuboid_server_start(ctx, PRIMES, streams=2, max_launch_units=1 << 14)
+    try:
+        before = cb.cuboid_server_stats_get(srv)["submitted"]
+        with pytest.raises(cb.CuboidError) as e:
+            cb.cuboid_server_submit_many(srv, [(1, 5, 1, 5), (6, 5, 1, 1), (1, 1, 1, 2)])
+        assert e.value.status == cb.E_RANGE and e.value.needed == 1
+        assert cb.cuboid_server_stats_get(srv)["submitted"] == before
+        tickets = cb.cuboid_server_submit_many(srv, rects)
+        assert len(set(int(t) for t in tickets)) == len(rects)
+        got = [cb.cuboid_server_poll(srv, int(t), len(PRIMES), cap=4096) for t in tickets]
+        stats = cb.cuboid_server_stats_get(srv)
+    finally:
+        cb.cuboid_server_stop(srv)
+    assert stats["completed"] == len(rects) and stats["max_admitted"] > 1
+    for rect, g in zip(rects, got):
+        assert g["status"] == cb.OK
+        _same(g, cb.cuboid_sieve_range(ctx, *rect, PRIMES, cap=4096))
+    _same(got[-2], oracle.sieve(1, 200, 1, 200, PRIMES))
+
+
 def test_poisson_replay_small(ctx):
     stream = wl.served_stream(duration=0.3, max_requests=600, area_hi=1e7)
     srv = cb.cuboid_server_start(ctx, PRIMES)
