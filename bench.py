@@ -95,21 +95,32 @@ def sweep_work_model(rects, k_dense, deep):
     return ops, lds, units, w7
 
 
-def measured_counters(units_live, sweep_s):
-    """VALU-issue and LDS-bandwidth fractions of the sweep from the committed
-    SQ counter record, only while the sweep kernel's source is the one the
-    counters were taken on: per-unit instruction counts times this launch's
-    units over its measured duration."""
+def _sweep_record(name, k_dense):
+    """The record of profiles/<name> taken on this sweep source and on the
+    kernel instance (dense-prime count) this launch runs, or None."""
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     try:
-        with open(os.path.join(here, "profiles", "sweep_counters.json")) as f:
-            rec = json.load(f)
         with open(os.path.join(here, "paper_1601_00636_amd", "csrc", "kernels_sieve.hip"), "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
+        with open(os.path.join(here, "profiles", name)) as f:
+            recs = json.load(f).get("records", [])
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha256") != sha:
+    for rec in recs:
+        if (rec.get("kernel_source_sha256") == sha and
+                ("sweep_kernel<%d," % k_dense) in (rec.get("kernel") or "")):
+            return rec
+    return None
+
+
+def measured_counters(units_live, sweep_s, k_dense):
+    """VALU-issue and LDS-bandwidth fractions of the sweep from the committed
+    SQ counter record, only while the sweep kernel's source and instance are
+    the ones the counters were taken on: per-unit instruction counts times
+    this launch's units over its measured duration."""
+    rec = _sweep_record("sweep_counters.json", k_dense)
+    if rec is None:
         return None
     pu = rec["per_unit"]
     valu = pu["SQ_INSTS_VALU"] * units_live
@@ -118,7 +129,7 @@ def measured_counters(units_live, sweep_s):
            "valu_issue_frac": valu * 4 / (SIMDS * CLOCK * sweep_s),
            "lds_insts_per_unit": pu["SQ_INSTS_LDS"],
            "lds_frac": lds_inst * 512 / sweep_s / LDS_PEAK,
-           "source": "profiles/sweep_counters.json"}
+           "source": "profiles/sweep_counters.json (%s)" % rec["kernel"]}
     if pu.get("SQ_ACTIVE_INST_LDS"):
         out["lds_bank_conflict_ratio"] = pu["SQ_LDS_BANK_CONFLICT"] / pu["SQ_ACTIVE_INST_LDS"]
     return out
@@ -139,19 +150,12 @@ def mean_depth(counts_total, n_surv, primes, trivial):
     return tot, k
 
 
-def measured_traffic():
+def measured_traffic(k_dense):
     """HBM traffic of the sweep from the committed rocprofv3 counter summary,
-    only while the sweep kernel's source is the one the counters were taken on."""
-    import hashlib
-    here = os.path.dirname(os.path.abspath(__file__))
-    try:
-        with open(os.path.join(here, "profiles", "sweep_traffic.json")) as f:
-            rec = json.load(f)
-        with open(os.path.join(here, "paper_1601_00636_amd", "csrc", "kernels_sieve.hip"), "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
-    except (OSError, ValueError):
-        return None, None
-    if rec.get("kernel_source_sha256") != sha:
+    only while the sweep kernel's source and instance are the ones the
+    counters were taken on."""
+    rec = _sweep_record("sweep_traffic.json", k_dense)
+    if rec is None:
         return None, None
     return rec["traffic_GBps"], rec["traffic_bytes_per_launch"]
 
@@ -528,8 +532,8 @@ def main():
     m_ops, m_lds, m_units, w7 = sweep_work_model(reqs, k_dense, deep)
     achieved = m_ops / (sweep_avg * 1e-3)
     lds_achieved = m_lds / (sweep_avg * 1e-3)
-    traffic_gbps, traffic_bytes = measured_traffic()
-    ctr = measured_counters(tim["units"], sweep_avg * 1e-3)
+    traffic_gbps, traffic_bytes = measured_traffic(k_dense)
+    ctr = measured_counters(tim["units"], sweep_avg * 1e-3, k_dense)
 
     res = {
         "metric": METRIC,

@@ -7,7 +7,8 @@ usage:
 
 `trace`: per-kernel dispatch counts and durations of a --kernel-trace run.
 `counters`: SQ counters of the sweep's largest dispatches per launch and per
-64x64 unit (profiles/sweep_counters.json, keyed by the source hash as below).
+64x64 unit (profiles/sweep_counters.json, one record per kernel instance,
+keyed by the source hash as below).
 `traffic`: FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the sweep kernel's
 largest launches, scaled by what the same counters read for a device copy of
 2^30 bytes (bench.py --calibrate-copy), and writes profiles/sweep_traffic.json
@@ -105,19 +106,20 @@ def counters(dbs, command, units):
     (bench.py turns the per-unit figures into issue fractions while the
     source is unchanged)."""
     rows = {}
+    kernel = None
     for db in dbs:
         c = sqlite3.connect(db)
-        for name, v, d in c.execute(
-                "select counter_name, value, duration from counters_collection where "
+        for kname, name, v, d in c.execute(
+                "select kernel_name, counter_name, value, duration from counters_collection where "
                 "kernel_name like '%sweep%' order by duration desc"):
             rows.setdefault(name, []).append((d, v))
-    rec = {"kernel_source_sha256": sweep_source_hash(), "units_per_launch": units,
-           "per_unit": {}}
+            kernel = kernel or _short(kname)
+    rec = {"kernel_source_sha256": sweep_source_hash(), "kernel": kernel,
+           "units_per_launch": units, "per_unit": {}}
     for name in sorted(rows):
         top = sorted(rows[name], reverse=True)[:2]
         rec["per_unit"][name] = sum(x[1] for x in top) / len(top) / units
-    with open(os.path.join(ROOT, "profiles", "sweep_counters.json"), "w") as f:
-        json.dump(rec, f, indent=1)
+    _merge_record(os.path.join(ROOT, "profiles", "sweep_counters.json"), rec)
     out = ["# SQ counters of the sweep kernel (batched 4096-rectangle workload)\n\n",
            "Commands (one counter group per run):\n\n    %s\n\n" % command.replace(";", "\n   "),
            "Averages over the 2 largest dispatches (the timed batched launches); "
@@ -130,6 +132,21 @@ def counters(dbs, command, units):
     return "".join(out)
 
 
+def _merge_record(path, rec):
+    """Keep one record per sweep kernel instance in a profiles JSON file
+    ({"records": [...]}), replacing an older record of the same instance."""
+    recs = []
+    try:
+        with open(path) as f:
+            old = json.load(f)
+        recs = old.get("records", [old] if "kernel_source_sha256" in old else [])
+    except (OSError, ValueError):
+        pass
+    recs = [r for r in recs if r.get("kernel") != rec["kernel"]] + [rec]
+    with open(path, "w") as f:
+        json.dump({"records": recs}, f, indent=1)
+
+
 def main(argv):
     if argv[0] == "trace":
         print(trace(argv[1], argv[2]))
@@ -138,8 +155,7 @@ def main(argv):
     elif argv[0] == "traffic":
         md, rec = traffic(argv[1], argv[2], argv[3], argv[4], argv[5])
         print(md)
-        with open(os.path.join(ROOT, "profiles", "sweep_traffic.json"), "w") as f:
-            json.dump(rec, f, indent=1)
+        _merge_record(os.path.join(ROOT, "profiles", "sweep_traffic.json"), rec)
     else:
         raise SystemExit(__doc__)
 
