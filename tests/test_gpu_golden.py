@@ -163,6 +163,26 @@ def test_rectangles_across_the_top_rows(ctx):
         assert got["n_survivors"] == r["n_survivors"]
 
 
+def test_top_rows_through_the_server(ctx):
+    # each top row as a rectangle over its region columns, queued on the
+    # request server at once: rows beyond the resident row table get their
+    # factor lists per request, q reaches 4.29e9
+    g = _top()
+    primes = g["primes"]
+    srv = cb.cuboid_server_start(ctx, primes, streams=2)
+    try:
+        tickets = cb.cuboid_server_submit_many(
+            srv, [(r["p"], r["p"], r["qmin"], r["qmax"]) for r in g["rows"]])
+        got = [cb.cuboid_server_poll(srv, int(t), len(primes), cap=1 << 12) for t in tickets]
+    finally:
+        cb.cuboid_server_stop(srv)
+    for r, x in zip(g["rows"], got):
+        assert x["status"] == cb.OK
+        assert x["n_pairs"] == r["n_pairs"]
+        assert [int(c) for c in x["counts"]] == r["counts"]
+        assert x["n_survivors"] == r["n_survivors"]
+
+
 def test_search_runs_to_the_end_of_the_range(ctx):
     # the background search from the first of the last four rows to p_max
     g = _top()
