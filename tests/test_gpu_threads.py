@@ -136,3 +136,52 @@ def test_stale_handle_after_a_new_context():
         assert cb.cuboid_sieve_range(new, 1, 200, 1, 200, wl.PRIMES_C1)["n_survivors"] == 26
     finally:
         assert cb.cuboid_destroy(new) == cb.OK
+
+
+def test_servers_and_plain_calls_on_one_context():
+    # two request servers with different prime lists and plain calls from
+    # other threads share one context at the same time: every result equals
+    # the plain call's alone
+    ctx = cb.cuboid_create(0)
+    try:
+        jobs = _jobs()[:6]
+        alone = [_run(ctx, j) for j in jobs]
+        mix_a = wl.random_rectangles(300, seed=71, max_coord=900000, max_side=3000)
+        mix_b = wl.random_rectangles(300, seed=72, max_coord=900000, max_side=3000)
+        ref_a = [cb.cuboid_sieve_range(ctx, *r, wl.PRIMES_BATCHED, cap=1 << 14) for r in mix_a]
+        ref_b = [cb.cuboid_sieve_range(ctx, *r, wl.PRIMES_C2, cap=1 << 14) for r in mix_b]
+        srv_a = cb.cuboid_server_start(ctx, wl.PRIMES_BATCHED, max_launch_units=1 << 12)
+        srv_b = cb.cuboid_server_start(ctx, wl.PRIMES_C2, max_launch_units=1 << 12)
+        got = [None] * len(jobs)
+        errors = []
+
+        def plain(i):
+            try:
+                got[i] = _run(ctx, jobs[i])
+            except Exception as e:   # noqa: BLE001 (reported below)
+                errors.append(e)
+
+        try:
+            threads = [threading.Thread(target=plain, args=(i,)) for i in range(len(jobs))]
+            for t in threads:
+                t.start()
+            ta = cb.cuboid_server_submit_many(srv_a, mix_a)
+            tb = [cb.cuboid_server_submit(srv_b, r) for r in mix_b]
+            res_a = [cb.cuboid_server_poll(srv_a, int(t), len(wl.PRIMES_BATCHED), cap=1 << 14)
+                     for t in ta]
+            res_b = [cb.cuboid_server_poll(srv_b, t, len(wl.PRIMES_C2), cap=1 << 14) for t in tb]
+            for t in threads:
+                t.join()
+        finally:
+            cb.cuboid_server_stop(srv_a)
+            cb.cuboid_server_stop(srv_b)
+        assert not errors, errors
+        for a, g in zip(alone, got):
+            _same(a, g)
+        for ref, x in zip(ref_a + ref_b, res_a + res_b):
+            assert x["status"] == cb.OK
+            assert x["n_pairs"] == ref["n_pairs"]
+            assert [int(c) for c in x["counts"]] == [int(c) for c in ref["counts"]]
+            assert [int(s) for s in x["survivors"]] == [int(s) for s in ref["survivors"]]
+    finally:
+        assert cb.cuboid_destroy(ctx) == cb.OK
