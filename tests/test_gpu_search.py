@@ -109,3 +109,28 @@ def test_search_errors(ctx):
         assert r["n_survivors"] == 26
     finally:
         cb.cuboid_search_stop(h)
+
+
+def test_plain_calls_while_a_search_runs(ctx):
+    # a background search and plain calls on the same context at the same
+    # time: the search's totals equal the region sieve's, the plain results
+    # equal the oracle's
+    primes = wl.PRIMES_PAPER
+    h = cb.cuboid_search_start(ctx, primes, 152, 3, p_end=20099)
+    try:
+        rects = [(1, 300, 1, 300), (5000, 5100, 7, 9000), (123456, 123470, 1, 40000)]
+        for _ in range(5):
+            for rect in rects:
+                got = cb.cuboid_sieve_range(ctx, *rect, wl.PRIMES_C2, cap=1 << 16)
+                ref = oracle.sieve(*rect, wl.PRIMES_C2, cap=1 << 16)
+                assert got["n_pairs"] == ref["n_pairs"]
+                assert [int(c) for c in got["counts"]] == [int(c) for c in ref["counts"]]
+                assert [int(x) for x in got["survivors"]] == [int(x) for x in ref["survivors"]]
+        _wait(h)
+    finally:
+        fin = cb.cuboid_search_stop(h)
+    reg = cb.cuboid_sieve_region(ctx, 152, 20099, primes)
+    assert fin["status"] == cb.OK
+    assert fin["p"] == 20100
+    assert fin["pairs"] == reg["n_pairs"]
+    assert fin["survivors"] == reg["n_survivors"]
